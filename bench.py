@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the multi-level greedy RBF mesh deformation hot path on one MI355X.
+
+One step = the whole path on one synthetic deformation: multi-level greedy selection of the
+control points on the surface (rbf_greedy_select) followed by the wall-distance-reduced volume
+update (rbf_volume_update). Inputs are resident in HBM before the timed region starts.
+
+Headline value: RBF evaluations per second of the volume update, i.e. the number of
+(reduced volume point, control point) pairs sum_l n_{D_l} N_{c,l} divided by the device time of
+the rbf_volume_update calls (hipEvents on the launch stream). Also reported: greedy time-to-eps,
+the roofline fraction of the volume kernel-sum launch (VALU issue bound), and the FP64 CPU oracle
+timed on this machine's host cores on the same workload.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload cfg1] [--precision fp64]
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RBF evals/s (volume update), greedy time-to-eps, p50/p99 request latency"
+VALU_LANE_OPS = 256 * 64 * 2.4e9          # 256 CUs x 64 lanes x 2.4 GHz
+MIN_SLOTS = {2: 17, 3: 20}                 # minimal VALU slots per pair (FP64), see the design doc
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    import synth
+
+    if name == "cfg1":
+        return synth.workload_cfg1(), ("2D NACA0012 multi-level: N_s=4000 surface, N_v=400000 O-mesh, "
+                                       "R_l=2c/0.5c/0.1c, eps=1e-5c, D=0.5c")
+    if name == "cfg0":
+        return synth.workload_cfg0(), "2D NACA0012 single level: N_s=400, N_v=20000, R=2c, eps=1e-5c, D=1c"
+    if name == "cfg2":
+        return synth.workload_cfg2(), ("3D swept wing ice horn: N_s=80000, N_v=4000000, R_l=3c/0.8c/0.2c, "
+                                       "eps=1e-4c, cap 4000, D=1c")
+    if name == "cfg3":
+        return synth.workload_cfg3(), ("3D swept wing bend+twist: N_s=80000, N_v=4000000, "
+                                       "R_l=3c/0.8c/0.2c, eps=1e-4c, cap 4000, D=1c")
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, ref, budget_s=12.0):
+    """FP64 oracle timed on the host cores: the volume update on the oracle's own control set,
+    repeated on the full reduced volume until about budget_s seconds have passed."""
+    import numpy as np
+
+    import oracle
+
+    o = oracle.get()
+    D = [w.D] * w.n_levels
+    xc = np.ascontiguousarray(w.xs[:, ref.ctrl_idx])
+    counts = [int((w.dwall < D[l]).sum()) for l in range(w.n_levels)]
+    pairs = sum(counts[l] * int(ref.level_off[l + 1] - ref.level_off[l]) for l in range(w.n_levels))
+    reps, t = 0, 0.0
+    while t < budget_s and reps < 1000:
+        t0 = time.perf_counter()
+        o.volume(w.radius, D, ref.level_off, xc, ref.alpha, w.xv, w.dwall)
+        t += time.perf_counter() - t0
+        reps += 1
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": pairs * reps / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"full reduced volume ({counts[0]} of {w.n_v} points) x {ref.level_off[-1]} "
+                      f"oracle control points, {reps} repetitions in {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg1")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2107_13887_amd import rbfdef
+
+    t0 = time.perf_counter()
+    w, desc = build_workload(args.workload)
+    log(f"bench: workload {w.name} built in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    xs = torch.from_numpy(w.xs).to(dev)
+    ds = torch.from_numpy(w.ds).to(dev)
+    xv = torch.from_numpy(w.xv).to(dev)
+    dw = torch.from_numpy(w.dwall).to(dev)
+    D = [w.D] * w.n_levels
+    ctx = rbfdef.rbf_ctx_create(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        g0 = time.perf_counter()
+        cs = rbfdef.rbf_greedy_select(ctx, xs, ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
+                                      seeds=w.seeds, precision=args.precision, want_residual=False)
+        g1 = time.perf_counter()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rbfdef.rbf_volume_update(ctx, w.radius, D, cs.level_off, cs.xc, cs.alpha, xv, dw,
+                                 precision=args.precision)
+        e1.record(stream)
+        return cs, g1 - g0, (e0, e1)
+
+    for i in range(args.warmup):
+        cs, _, _ = step()
+        torch.cuda.synchronize()
+        log(f"bench: warmup {i + 1}/{args.warmup} done ({cs.total} control points)")
+    rbfdef.rbf_ctx_set_timing(ctx, True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    greedy_t, events = [], []
+    for i in range(args.steps):
+        cs, tg, ev = step()
+        greedy_t.append(tg)
+        events.append(ev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    vol_ms = [a.elapsed_time(b) for a, b in events]
+    k_ms, k_n = rbfdef.rbf_ctx_kernel_time(ctx, "volume_ksum_" + args.precision)
+    log(f"bench: {args.steps} steps in {wall:.3f}s")
+
+    n_c = [cs.level_off[l + 1] - cs.level_off[l] for l in range(w.n_levels)]
+    n_d = [int((w.dwall < D[l]).sum()) for l in range(w.n_levels)]
+    pairs = sum(n_d[l] * n_c[l] for l in range(w.n_levels))
+    value = pairs * args.steps / (sum(vol_ms) / 1e3)
+    avg_kernel_s = (k_ms / k_n) / 1e3 if k_n else float("nan")
+    peak = VALU_LANE_OPS / MIN_SLOTS[w.dim] / 1e9
+    achieved = pairs / avg_kernel_s / 1e9
+
+    # Parity and CPU baseline outside the timed region.
+    ref = oracle.get().greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
+                              seeds=w.seeds)
+    same = bool(np.array_equal(cs.ctrl_idx[: cs.total].cpu().numpy(), ref.ctrl_idx))
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, ref)
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {desc}", "precision": args.precision,
+                   "control_points_per_level": n_c, "reduced_volume_points_per_level": n_d,
+                   "pairs_per_volume_update": pairs, "parallelism": "single GPU"},
+        "greedy_time_to_eps_s": statistics.median(greedy_t),
+        "greedy_iterations": cs.n_iterations,
+        "volume_update_ms": statistics.median(vol_ms),
+        "selection_identical_to_oracle": same,
+        "p50_latency_ms": None,
+        "p99_latency_ms": None,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "volume_ksum_" + args.precision,
+                     "kernel_avg_ms": avg_kernel_s * 1e3, "kernel_launches": k_n},
+        "cpu_baseline": cpu,
+    }
+    rbfdef.rbf_ctx_destroy(ctx)
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

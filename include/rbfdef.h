@@ -1,0 +1,212 @@
+/*
+ * rbfdef.h -- C ABI of an MI355X (gfx950) library for multi-level greedy radial-basis-function
+ * mesh deformation with wall-distance volume reduction.
+ *
+ * Method: Morelli, Bellosta, Guardone, "Efficient Radial Basis Function Mesh Deformation Methods
+ * for Aircraft Icing" (arXiv:2107.13887). Section 2 defines the interpolant (eq. (1)), its weights
+ * (eq. (9)) and the Wendland C2 basis (eq. (2), Table 1); Section 3 the greedy selection (eq. (12))
+ * and its multi-level form (eq. (19)); Section 4 the wall-distance weight psi and the weighted
+ * volume update (eq. (23)).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns rbf_status: 0 success, > 0 success with a warning, < 0 error. No call
+ *     throws or aborts. On error the outputs are unspecified. rbf_last_error() gives a readable
+ *     detail of the last error raised on the calling thread.
+ *   - Arrays are structure-of-arrays: coordinate or component k of point i lives at
+ *     a[k * ld + i], with ld = the number of points unless a leading dimension is passed.
+ *   - Pointers marked "device" are GPU memory of the context's device, owned by the caller and
+ *     valid for the duration of the call (or, for rbf_submit, until the request is DONE).
+ *     Pointers marked "host" are ordinary host memory, read during the call only.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the default stream). Calls marked
+ *     "blocking" return after their device work has finished; the others only enqueue it.
+ *   - All device memory the library needs besides the caller's buffers comes from the context
+ *     and counts against its HBM budget; RBF_E_NOMEM is returned when it would be exceeded.
+ *   - Calls on one context are not thread-safe except rbf_submit, rbf_poll and rbf_wait.
+ */
+#ifndef RBFDEF_H
+#define RBFDEF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rbf_status;
+#define RBF_OK 0
+#define RBF_W_CAP 1          /* selection stopped at max_ctrl_total */
+#define RBF_W_BREAKDOWN 2    /* a level stopped because the next Cholesky pivot was not positive */
+#define RBF_E_INVALID (-1)   /* bad argument: dimension, size, radius, tolerance, seed, NaN */
+#define RBF_E_NOMEM (-2)     /* the context's HBM budget (or the device) cannot hold the work */
+#define RBF_E_NOT_SPD (-3)   /* Phi_cc not numerically positive definite (e.g. repeated points) */
+#define RBF_E_DEVICE (-4)    /* a HIP runtime call failed */
+#define RBF_E_NOT_FOUND (-5) /* unknown ticket or geometry */
+#define RBF_E_BUSY (-6)      /* geometry still referenced by queued or running requests */
+
+#define RBF_FP64 0   /* every kernel sum in FP64 */
+#define RBF_MIXED 1  /* volume kernel sums in FP32 on locally shifted coordinates with an FP64
+                        accumulator; greedy factor, convergence check and residuals stay FP64 */
+
+#define RBF_STOP_SKIPPED (-1)     /* level not run: an earlier level already met eps_abs */
+#define RBF_STOP_EPS 0            /* max ||E|| fell below the level's target */
+#define RBF_STOP_CAP 1            /* max_ctrl_total reached */
+#define RBF_STOP_ALL_SELECTED 2   /* every surface point is a control point of the level */
+#define RBF_STOP_BREAKDOWN 3      /* next pivot d^2 = phi(0) - l.l not positive */
+
+#define RBF_MAX_LEVELS 8
+
+typedef struct rbf_ctx_s *rbf_ctx;
+typedef struct rbf_geom_s *rbf_geom;
+typedef uint64_t rbf_ticket;
+
+/* ---------------------------------------------------------------------------------------------
+ * Context: one GPU, one HBM budget, the pool every internal buffer comes from.
+ * device: HIP device ordinal. hbm_budget_bytes: ceiling on library-owned device memory
+ * (0 = 90% of the device's free memory). The context owns its pool and a scheduler thread for
+ * rbf_submit; rbf_ctx_destroy waits for running requests, then frees everything.
+ * ------------------------------------------------------------------------------------------- */
+rbf_status rbf_ctx_create(int32_t device, uint64_t hbm_budget_bytes, rbf_ctx *out);
+rbf_status rbf_ctx_destroy(rbf_ctx ctx);
+const char *rbf_status_str(rbf_status s);
+const char *rbf_last_error(void);
+/* Library-owned device bytes currently held by the context (pool high-water included). */
+uint64_t rbf_ctx_bytes_in_use(rbf_ctx ctx);
+
+/* Kernel timing for measurement: when enabled, the main kernel-sum launch of every call is
+ * bracketed by a pair of hipEvents on its stream (adds two event records per launch). Kernel
+ * names: "volume_ksum_fp64", "volume_ksum_mixed", "surface_ksum_fp64", "surface_ksum_mixed".
+ * rbf_ctx_kernel_time waits for the recorded events and returns the summed device time (ms)
+ * and the number of launches since timing was last enabled; set_timing clears the totals. */
+rbf_status rbf_ctx_set_timing(rbf_ctx ctx, int32_t enabled);
+rbf_status rbf_ctx_kernel_time(rbf_ctx ctx, const char *kernel, double *total_ms, int64_t *launches);
+
+/* ---------------------------------------------------------------------------------------------
+ * Greedy parameters (Section 3). The paper's defaults: one support radius R for all levels,
+ * per-level reduction 0.1 of the normalized error, first control point = the first surface
+ * point. The target of a non-final level l is max(eps_abs, level_reduction * max_i ||dS_l,i||);
+ * the final level runs to eps_abs. Norms are per-point Euclidean norms of the dim components.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t dim;                    /* 2 or 3 */
+    int32_t n_levels;               /* 1 .. RBF_MAX_LEVELS */
+    double radius[RBF_MAX_LEVELS];  /* support radius R_l > 0 of level l, eq. (2) */
+    double eps_abs;                 /* stop once max_i ||E_i|| < eps_abs (same units as dS) */
+    double level_reduction;         /* rho in (0, 1] */
+    int64_t max_ctrl_total;         /* cap on sum_l N_c,l, >= 1 */
+    const int64_t *seed_idx;        /* host: seed point indices of all levels, CSR by seed_off */
+    const int32_t *seed_off;        /* host [n_levels + 1]; NULL = paper default {0} at level 0 */
+    int32_t precision;              /* RBF_FP64 or RBF_MIXED */
+} rbf_greedy_params;
+
+/* Result of a greedy selection. The caller sets the four device pointers and `capacity`
+ * (>= max_ctrl_total); the library fills the rest. Levels are concatenated: level l owns
+ * positions level_off[l] .. level_off[l+1]-1 of ctrl_idx, xc and alpha. */
+typedef struct {
+    int64_t capacity;                      /* in: leading dimension of xc and alpha */
+    int64_t *ctrl_idx;                     /* device [capacity]: surface indices, selection order */
+    double *xc;                            /* device [dim][capacity]: their coordinates */
+    double *alpha;                         /* device [dim][capacity]: weights, eq. (9) per level */
+    double *e_final;                       /* device [dim][n_s] or NULL: residual after the last level */
+    int32_t n_levels_used;                 /* out */
+    int32_t stop_reason;                   /* out: stop reason of the last level run */
+    int32_t level_off[RBF_MAX_LEVELS + 1]; /* out */
+    int32_t level_stop[RBF_MAX_LEVELS];    /* out: RBF_STOP_* per level */
+    double level_max_err[RBF_MAX_LEVELS];  /* out: max_i ||E_i|| (FP64) at each level close */
+    int64_t n_iterations;                  /* out: argmax selections made (seeds excluded) */
+} rbf_ctrl_set;
+
+/* Multi-level greedy surface point selection, Section 3. Per level l: start from the residual
+ * dS_l (dS_0 = ds), append the seeds, then repeatedly take the weights of Phi_cc alpha = dS_l,c
+ * (eq. (9) on the control set), the error E = dS_l - Phi_sc alpha (eq. (12)) and append the
+ * unselected point of largest ||E_i|| (lowest index on exact ties) until max ||E|| is below the
+ * level target; then dS_{l+1} = E. The GPU keeps the Newton basis of the control set at every
+ * surface point (the Cholesky factor of Phi_cc bordered by one row per added point), so each
+ * iteration costs one rank-one update and one argmax, with no triangular solve.
+ * xs, ds: device [dim][n_s] FP64. Blocking. Returns RBF_W_CAP / RBF_W_BREAKDOWN as warnings. */
+rbf_status rbf_greedy_select(rbf_ctx ctx, const rbf_greedy_params *params, int64_t n_s,
+                             const double *xs, const double *ds, rbf_ctrl_set *out, void *stream);
+
+/* Weights of the interpolant through n_c given points, eq. (9): Phi_cc alpha = dsc with
+ * Phi_cc[i][j] = phi(||x_i - x_j|| / radius). FP64 blocked Cholesky (trailing updates on FP64
+ * matrix cores) and triangular solves. xc, dsc, alpha: device [dim][n_c]. Blocking.
+ * RBF_E_NOT_SPD when a pivot is not positive (repeated or numerically coincident points). */
+rbf_status rbf_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c,
+                             const double *xc, const double *dsc, double *alpha, void *stream);
+
+/* Volume update with wall-distance reduction, eqs. (19) and (23):
+ *   dv_v = sum_l psi(dwall_v / D_l) sum_{c in level l} phi(||xv_v - xc_c|| / radius_l) alpha_c
+ * with psi(xi) = 1 - xi on [0, 1) and 0 beyond, so points with dwall_v >= max_l D_l get +0.0
+ * and are skipped (the volume point reduction of Section 4).
+ * radius, D: host [n_levels]; level_off: host [n_levels + 1] offsets into xc/alpha;
+ * xc, alpha: device [dim][ld_ctrl]; xv: device [dim][n_v]; dwall: device [n_v];
+ * dv: device [dim][n_v] output (fully written). precision: RBF_FP64 or RBF_MIXED.
+ * Enqueued on `stream`; returns before the device work finishes. */
+rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
+                             const double *D, const int32_t *level_off, int64_t ld_ctrl,
+                             const double *xc, const double *alpha, int64_t n_v, const double *xv,
+                             const double *dwall, double *dv, int32_t precision, void *stream);
+
+/* Interpolant evaluation, eq. (1) with the support of eq. (2), at n_p points:
+ *   out_k(p) = base_k(p) - sign * sum_c phi(||x_p - xc_c|| / radius) alpha_k,c
+ * sign = -1 with base = NULL gives the plain interpolant; sign = +1 with base = dS gives the
+ * greedy error of eq. (12). xc, alpha: device [dim][ld_ctrl]; xp, base, out: device [dim][n_p].
+ * Enqueued on `stream`. */
+rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, int64_t ld_ctrl,
+                        const double *xc, const double *alpha, int64_t n_p, const double *xp,
+                        const double *base, double sign, double *out, int32_t precision,
+                        void *stream);
+
+/* ---------------------------------------------------------------------------------------------
+ * Serving: resident geometries and asynchronous deformation requests with continuous batching.
+ * A geometry (surface + volume + wall distance) is copied once into the pool and kept, volume
+ * sorted by wall distance so each request's reduced volume is a prefix. Requests that arrive
+ * while others run are admitted as soon as a slot and enough of the HBM budget are free; their
+ * kernels overlap on separate streams. A request with warm_start seeds each level with the
+ * control set the geometry's previous request selected (successive icing steps).
+ * ------------------------------------------------------------------------------------------- */
+
+/* xs: device [dim][n_s]; xv: device [dim][n_v]; dwall: device [n_v] or NULL (then the distance
+ * to the nearest surface point is computed on the device). Blocking. */
+rbf_status rbf_geom_create(rbf_ctx ctx, int32_t dim, int64_t n_s, const double *xs, int64_t n_v,
+                           const double *xv, const double *dwall, rbf_geom *out);
+/* RBF_E_BUSY while requests on the geometry are queued or running. */
+rbf_status rbf_geom_release(rbf_ctx ctx, rbf_geom geom);
+
+typedef struct {
+    rbf_geom geom;
+    const double *ds;          /* device [dim][n_s], caller-owned until the request is DONE */
+    rbf_greedy_params params;  /* copied at submit (seed arrays included) */
+    double D[RBF_MAX_LEVELS];  /* wall-distance support per level */
+    int32_t warm_start;        /* 1: seed each level with this geometry's previous control set */
+    double *dv;                /* device [dim][n_v] output in the geometry's original order */
+    rbf_ctrl_set *out;         /* NULL, or caller-owned until DONE (device arrays as above) */
+} rbf_request;
+
+#define RBF_REQ_QUEUED 0
+#define RBF_REQ_RUNNING 1
+#define RBF_REQ_DONE 2
+#define RBF_REQ_FAILED 3
+
+typedef struct {
+    int32_t state;       /* RBF_REQ_* */
+    rbf_status result;   /* final status once DONE or FAILED */
+    double t_arrive;     /* seconds on the library's monotonic clock */
+    double t_admit;
+    double t_start;
+    double t_done;
+} rbf_req_info;
+
+/* Non-blocking. RBF_E_NOMEM if the request could never fit the budget. */
+rbf_status rbf_submit(rbf_ctx ctx, const rbf_request *req, rbf_ticket *out);
+/* Non-blocking status query. A DONE/FAILED ticket stays queryable until rbf_wait returns it. */
+rbf_status rbf_poll(rbf_ctx ctx, rbf_ticket ticket, rbf_req_info *out);
+/* Blocks until the request is DONE or FAILED, fills *out, then forgets the ticket. */
+rbf_status rbf_wait(rbf_ctx ctx, rbf_ticket ticket, rbf_req_info *out);
+/* The library's monotonic clock, in seconds (same clock as rbf_req_info). */
+double rbf_now(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBFDEF_H */

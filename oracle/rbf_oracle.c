@@ -18,12 +18,14 @@
  * squared norms compared and the lowest index winning ties; a non-final level ends once
  * max||E|| < max(eps, rho * max||dS_l||); the last level ends at max||E|| < eps; points already
  * selected in a level are not candidates; eta = ||r - r_c|| / R_l everywhere; phi(eta >= 1) = 0
- * and psi(xi >= 1) = 0 exactly; a non-positive Cholesky pivot stops the level (breakdown).
+ * and psi(xi >= 1) = 0 exactly; a Cholesky pivot d^2 not above (n + 1) * 2^-52, i.e. zero within
+ * the rounding of l.l, stops the level (breakdown).
  *
  * OpenMP parallelises only over independent points. Each sum over control points runs serially
  * in selection order, so results are reproducible bit for bit for a given binary. The library
  * is built with -ffp-contract=off so no multiply-add is fused behind the reader's back.
  */
+#include <float.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -118,7 +120,7 @@ int orc_solve_weights(int dim, double radius, int64_t n_c, const double *xc, con
             double s = L[i * n_c + j];
             for (int64_t k = 0; k < j; ++k) s -= L[i * n_c + k] * L[j * n_c + k];
             if (i == j) {
-                if (!(s > 0.0)) { free(L); return ORC_E_NOT_SPD; }
+                if (!(s > (double)(i + 1) * DBL_EPSILON)) { free(L); return ORC_E_NOT_SPD; }
                 L[i * n_c + i] = sqrt(s);
             } else {
                 L[i * n_c + j] = s / L[j * n_c + j];
@@ -173,7 +175,8 @@ static int chol_append(packed_chol *f, int dim, const double *xs, int64_t n_s, d
         ll += row[i] * row[i];
     }
     double d2 = orc_wendland_c2(0.0) - ll;
-    if (!(d2 > 0.0)) return 1;
+    /* l.l carries about (n + 1) ulps of rounding: a pivot below that is numerically zero. */
+    if (!(d2 > (double)(n + 1) * DBL_EPSILON)) return 1;
     row[n] = sqrt(d2);
     f->n = n + 1;
     return 0;

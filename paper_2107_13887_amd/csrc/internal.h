@@ -1,0 +1,179 @@
+// Internal declarations shared by the library's translation units: the context, its device
+// pool, error plumbing and the kernel launchers. Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rbfdef.h"
+
+namespace rbf {
+
+// ---- errors ------------------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+rbf_status fail(rbf_status s, const char *fmt, ...);
+
+#define RBF_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ::rbf::fail(RBF_E_DEVICE, "%s failed: %s (%s:%d)", #call,                   \
+                               hipGetErrorString(e_), __FILE__, __LINE__);                     \
+    } while (0)
+
+#define RBF_TRY(expr)                                                                          \
+    do {                                                                                       \
+        rbf_status s_ = (expr);                                                                \
+        if (s_ < 0) return s_;                                                                 \
+    } while (0)
+
+// ---- device pool ---------------------------------------------------------------------------------
+// Caching allocator bounded by the context's HBM budget. Blocks freed with free_after() stay
+// unavailable until the work already enqueued on that stream has finished (stream-ordered reuse).
+class Pool {
+  public:
+    Pool(int device, uint64_t budget) : device_(device), budget_(budget) {}
+    ~Pool();
+    rbf_status alloc(void **p, size_t bytes);
+    void free_now(void *p);                       // caller guarantees no pending device use
+    rbf_status free_after(void *p, hipStream_t s);  // reusable once s has passed this point
+    uint64_t in_use() const { return held_; }
+    uint64_t budget() const { return budget_; }
+    uint64_t live() const { return live_; }
+
+  private:
+    void reclaim_locked();
+    static size_t round_up(size_t b);
+    int device_;
+    uint64_t budget_;
+    uint64_t held_ = 0;   // bytes obtained from hipMalloc and not yet returned to the driver
+    uint64_t live_ = 0;   // bytes currently handed out
+    std::mutex mu_;
+    std::multimap<size_t, void *> free_;           // size -> block
+    std::unordered_map<void *, size_t> size_of_;
+    struct Deferred { void *p; hipEvent_t ev; };
+    std::deque<Deferred> deferred_;
+};
+
+// RAII device buffer from the pool. release_after() hands it back stream-ordered.
+struct DevBuf {
+    Pool *pool = nullptr;
+    void *ptr = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : pool(o.pool), ptr(o.ptr) { o.ptr = nullptr; }
+    ~DevBuf() { if (ptr && pool) pool->free_now(ptr); }
+    rbf_status get(Pool *pl, size_t bytes) {
+        if (ptr && pool) pool->free_now(ptr);
+        pool = pl;
+        ptr = nullptr;
+        return pl->alloc(&ptr, bytes);
+    }
+    void release_after(hipStream_t s) {
+        if (ptr && pool) pool->free_after(ptr, s);
+        ptr = nullptr;
+    }
+    template <class T> T *as() const { return static_cast<T *>(ptr); }
+};
+
+class Server;   // serving loop (serve.cpp)
+
+struct Geometry {
+    int32_t dim = 0;
+    int64_t n_s = 0, n_v = 0;
+    DevBuf xs, xv_sorted, d_sorted, perm;   // volume sorted by wall distance, perm: sorted -> orig
+    // Control sets of the last finished request (warm start), host copies per level.
+    std::vector<std::vector<int64_t>> last_ctrl;
+    int32_t refs = 0;
+    uint64_t bytes = 0;
+};
+
+}  // namespace rbf
+
+namespace rbf {
+// Optional per-kernel device timers (hipEvent pairs), resolved lazily when queried.
+struct KernelTimers {
+    std::mutex mu;
+    bool enabled = false;
+    struct Pending { std::string name; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    std::map<std::string, std::pair<double, int64_t>> total;   // name -> (ms, launches)
+    void begin(hipEvent_t *a, hipStream_t s);
+    void end(const char *name, hipEvent_t a, hipStream_t s);
+    void resolve();
+};
+}  // namespace rbf
+
+struct rbf_ctx_s {
+    rbf::KernelTimers timers;
+    int device = 0;
+    hipDeviceProp_t prop{};
+    std::unique_ptr<rbf::Pool> pool;
+    rbf::Server *server = nullptr;   // created on first submit, deleted by server_shutdown
+    std::mutex geom_mu;
+    std::unordered_map<rbf_geom, std::unique_ptr<rbf::Geometry>> geoms;
+    int n_cu = 256;
+};
+
+struct rbf_geom_s {};  // opaque handle; the address keys the context's geometry table
+
+namespace rbf {
+
+// ---- kernel sums (ksum.hip) ---------------------------------------------------------------------
+struct SumLevel {
+    double inv_r;     // 1 / R_l
+    double D;         // wall-distance support D_l, or 0 when psi is not applied
+    int64_t c_begin;  // range in the packed control array
+    int64_t c_end;
+};
+
+struct SumProblem {
+    int32_t dim = 3;
+    int32_t n_levels = 1;
+    SumLevel lv[RBF_MAX_LEVELS];
+    int64_t ld_ctrl = 0;          // leading dimension of xc / alpha
+    const double *xc = nullptr;   // [dim][ld_ctrl]
+    const double *alpha = nullptr;
+    int64_t n_p = 0;              // number of points
+    const double *xp = nullptr;   // [dim][n_p]
+    const double *dwall = nullptr;  // [n_p] or null (psi = 1)
+    const double *base = nullptr;   // out = base - sign * sum (base null: 0)
+    double sign = -1.0;
+    double *out = nullptr;        // [dim][n_p], fully written
+    int32_t precision = RBF_FP64;
+    bool sorted_by_d = false;     // dwall ascending: the reduced volume is a prefix
+};
+
+// Enqueues the whole evaluation on `s`; scratch comes from the pool and is released
+// stream-ordered, so the call does not wait for the device.
+rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s);
+
+// ---- greedy (greedy.hip) ------------------------------------------------------------------------
+rbf_status run_greedy(rbf_ctx ctx, const rbf_greedy_params &p, int64_t n_s, const double *xs,
+                      const double *ds, rbf_ctrl_set *out, hipStream_t s);
+
+// ---- dense solves (chol.hip) --------------------------------------------------------------------
+rbf_status run_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c,
+                             const double *xc, const double *dsc, double *alpha, hipStream_t s);
+
+// ---- validation helpers (capi.cpp) ---------------------------------------------------------------
+rbf_status validate_params(const rbf_greedy_params &p, int64_t n_s);
+double now_seconds();
+
+// ---- serving (serve.cpp) --------------------------------------------------------------------------
+void server_shutdown(rbf_ctx ctx);   // stops the scheduler thread and drops its state
+
+}  // namespace rbf

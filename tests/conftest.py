@@ -21,3 +21,20 @@ def orc():
     import oracle
 
     return oracle.get()
+
+
+@pytest.fixture(scope="session")
+def gctx():
+    """One library context on cuda:0 for the GPU tests."""
+    import torch
+
+    from paper_2107_13887_amd import rbfdef
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    h = rbfdef.rbf_ctx_create(0)
+    yield h
+    torch.cuda.synchronize()
+    rbfdef.rbf_ctx_destroy(h)
+

@@ -1,0 +1,153 @@
+"""GPU parity of the multi-level greedy selection (Section 3) against the FP64 oracle.
+
+Bar: the control points of every level identical to the oracle's (same indices, same order);
+the final surface residual and the volume update built from the GPU's control set within
+1e-10 of the result's scale plus 64 u S, S the magnitude of the summed terms (the rounding floor
+of any FP64 evaluation of these sums); the weights themselves within 1e-6 normwise (they carry the condition
+number of Phi_cc, which the interpolant values do not).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import fp64_bound, normwise, sum_magnitude, to_dev
+from paper_2107_13887_amd import rbfdef
+
+pytestmark = pytest.mark.gpu
+
+
+def _greedy_both(gctx, orc, w, precision="fp64"):
+    print(f"case {w.name} n_s={w.n_s} levels={w.radius} eps={w.eps} {precision}", flush=True)
+    ref = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds)
+    cs = rbfdef.rbf_greedy_select(gctx, to_dev(w.xs), to_dev(w.ds), w.radius, w.eps, rho=w.rho,
+                                  cap=w.cap_total(), seeds=w.seeds, precision=precision)
+    torch.cuda.synchronize()
+    return ref, cs
+
+
+def _check_same(orc, w, ref, cs):
+    assert cs.n_levels_used == ref.n_levels_used
+    assert cs.level_off[: ref.n_levels_used + 1] == list(ref.level_off[: ref.n_levels_used + 1])
+    got = cs.ctrl_idx[: cs.total].cpu().numpy()
+    assert np.array_equal(got, ref.ctrl_idx)
+    assert cs.level_stop[: ref.n_levels_used] == list(ref.level_stop[: ref.n_levels_used])
+    scale = np.sqrt((w.ds ** 2).sum(0)).max()
+    S = sum_magnitude(orc, w.radius, ref.level_off, w.xs[:, ref.ctrl_idx], ref.alpha, w.xs)
+    tol = fp64_bound(scale, S)
+    e = cs.e_final.cpu().numpy()
+    err = np.sqrt(((e - ref.e_final) ** 2).sum(0)).max()
+    a = cs.alpha[:, : cs.total].cpu().numpy()
+    print(f"residual error {err:.3e} (bound {tol:.3e}, sum magnitude {S:.3e}); "
+          f"weights normwise {normwise(a, ref.alpha):.3e}")
+    assert err <= tol
+    assert normwise(a, ref.alpha) <= 1e-6
+    xc = cs.xc[:, : cs.total].cpu().numpy()
+    assert np.array_equal(xc, w.xs[:, ref.ctrl_idx])
+    for l in range(ref.n_levels_used):
+        assert abs(cs.level_max_err[l] - ref.level_max_err[l]) <= tol
+
+
+@pytest.mark.parametrize("seed,dim,n_s,radius,eps", [
+    (1, 2, 150, [1.5], 1e-6),
+    (2, 3, 333, [2.0, 0.7], 1e-6),
+    (3, 3, 500, [1.0, 0.4, 0.2], 1e-7),
+    (4, 2, 1000, [2.0, 0.5, 0.1], 1e-7),
+])
+def test_greedy_random(gctx, orc, seed, dim, n_s, radius, eps):
+    w = synth.random_workload(100 + seed, dim, n_s, 10, radius, eps)
+    ref, cs = _greedy_both(gctx, orc, w)
+    _check_same(orc, w, ref, cs)
+
+
+def test_greedy_cfg0_full(gctx, orc):
+    """2D single level, 400 surface points, two seeds, jitter-driven selection of almost all
+    points (the most ill-conditioned case)."""
+    w = synth.workload(0)
+    ref, cs = _greedy_both(gctx, orc, w)
+    _check_same(orc, w, ref, cs)
+
+
+def test_greedy_cfg1_full_and_volume(gctx, orc):
+    """2D multi-level, 4000 surface points / 400k volume points: identical control sets and the
+    volume update within 1e-10 of the oracle's at every point."""
+    w = synth.workload(1)
+    ref, cs = _greedy_both(gctx, orc, w)
+    _check_same(orc, w, ref, cs)
+    D = [w.D] * w.n_levels
+    dv = rbfdef.rbf_volume_update(gctx, w.radius, D, cs.level_off, cs.xc, cs.alpha, to_dev(w.xv),
+                                  to_dev(w.dwall))
+    torch.cuda.synchronize()
+    xc = w.xs[:, ref.ctrl_idx]
+    ref_dv = orc.volume(w.radius, D, ref.level_off, xc, ref.alpha, w.xv, w.dwall)
+    scale = np.sqrt((ref_dv ** 2).sum(0)).max()
+    S = sum_magnitude(orc, w.radius, ref.level_off, xc, ref.alpha, w.xv, w.dwall, D)
+    err = np.sqrt(((dv.cpu().numpy() - ref_dv) ** 2).sum(0)).max()
+    print(f"volume error {err:.3e} = {err / scale:.3e} normwise (bound {fp64_bound(scale, S):.3e})")
+    assert err <= fp64_bound(scale, S)
+
+
+def test_greedy_all_selected_and_cap(gctx, orc):
+    w = synth.random_workload(7, 3, 90, 10, [1.2], 0.0)
+    ref, cs = _greedy_both(gctx, orc, w)
+    assert cs.level_stop[0] == 2 and cs.total == 90
+    assert np.abs(cs.e_final.cpu().numpy()).max() <= 1e-12 * np.abs(w.ds).max()
+    _check_same(orc, w, ref, cs)
+    cs2 = rbfdef.rbf_greedy_select(gctx, to_dev(w.xs), to_dev(w.ds), [1.2, 0.5], 0.0, cap=25)
+    assert cs2.status == rbfdef.RBF_W_CAP and cs2.total == 25
+
+
+def test_greedy_ties_go_to_lowest_index(gctx):
+    x = np.array([0.0, -0.3, 0.3, -0.6, 0.6])
+    xs = np.stack([x, np.zeros_like(x)])
+    ds = np.stack([np.array([0.0, 1.0, 1.0, 0.5, 0.5]), np.zeros(5)])
+    cs = rbfdef.rbf_greedy_select(gctx, to_dev(xs), to_dev(ds), [1.0], 0.0, cap=3, seeds=[[0]])
+    assert list(cs.ctrl_idx[:3].cpu().numpy()) == [0, 1, 2]
+
+
+def test_greedy_breakdown_on_duplicate_point(gctx, orc):
+    w = synth.random_workload(8, 2, 10, 10, [1.0], 0.0)
+    xs = np.concatenate([w.xs, w.xs[:, :1]], axis=1)
+    ds = np.concatenate([w.ds, w.ds[:, :1]], axis=1)
+    ref = orc.greedy(2, xs, ds, [1.0], 0.0, cap=11)
+    cs = rbfdef.rbf_greedy_select(gctx, to_dev(xs), to_dev(ds), [1.0], 0.0, cap=11)
+    assert cs.status == rbfdef.RBF_W_BREAKDOWN
+    assert cs.level_stop[0] == ref.level_stop[0] == 3
+    assert np.array_equal(cs.ctrl_idx[: cs.total].cpu().numpy(), ref.ctrl_idx)
+    assert torch.isfinite(cs.alpha[:, : cs.total]).all()
+
+
+def test_greedy_rejects_bad_input(gctx):
+    xs = torch.zeros((2, 10), dtype=torch.float64, device="cuda:0")
+    ds = torch.zeros((2, 10), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(rbfdef.RbfError):
+        rbfdef.rbf_greedy_select(gctx, xs, ds, [1.0], 1e-6, seeds=[[3, 3]])
+    with pytest.raises(rbfdef.RbfError):
+        rbfdef.rbf_greedy_select(gctx, xs, ds, [1.0], 1e-6, seeds=[[12]])
+    bad = ds.clone()
+    bad[0, 3] = float("nan")
+    with pytest.raises(rbfdef.RbfError):
+        rbfdef.rbf_greedy_select(gctx, xs + torch.arange(10, device="cuda:0"), bad, [1.0], 1e-6)
+
+
+def test_weight_solve_matches_oracle(gctx, orc):
+    rng = np.random.default_rng(61)
+    for dim, n, R in ((2, 37, 1.5), (3, 200, 2.0), (3, 513, 1.0), (2, 1000, 0.6)):
+        xc = rng.uniform(-1, 1, (dim, n))
+        dsc = rng.uniform(-0.05, 0.05, (dim, n))
+        print(f"case solve dim={dim} n={n} R={R}", flush=True)
+        st, ref = orc.solve_weights(R, xc, dsc)
+        assert st == 0
+        a = rbfdef.rbf_solve_weights(gctx, R, to_dev(xc), to_dev(dsc))
+        torch.cuda.synchronize()
+        a = a.cpu().numpy()
+        assert normwise(a, ref) <= 1e-7
+        back = orc.evaluate(R, xc, a, xc)
+        assert np.abs(back - dsc).max() <= 1e-11
+
+
+def test_weight_solve_not_spd(gctx):
+    xc = np.array([[0.0, 0.3, 0.3], [0.0, 0.1, 0.1]])
+    with pytest.raises(rbfdef.RbfError) as e:
+        rbfdef.rbf_solve_weights(gctx, 1.0, to_dev(xc), to_dev(np.zeros((2, 3))))
+    assert e.value.status == rbfdef.RBF_E_NOT_SPD
