@@ -15,20 +15,29 @@
 // back substitution L^T alpha = y, and the level residual dS_{l+1} = dS_l - Phi_sC alpha is then
 // recomputed from alpha by the FP64 kernel sum (the same quantity the paper's loop produces).
 //
-// Kernels per iteration: g_select (one workgroup: argmax of the per-block maxima, stop tests,
-// row extraction, pivot) and g_update (one workgroup per 64 surface points: new column, error
-// update, block argmax). Reductions run in a fixed order; squared norms are formed without fused
-// multiply-adds so they equal the oracle's formula term by term.
+// Execution. A level runs as one persistent cooperative kernel: a select phase (one workgroup:
+// argmax of the per-tile maxima, stop tests, row extraction, pivot) and an update phase (all
+// workgroups, 64 surface points per tile: new column, error update, tile argmax), separated by
+// grid-wide barriers, so an iteration costs two barriers instead of two kernel launches. When a
+// cooperative launch is not possible the same phases run as two kernels per iteration.
+// Reductions run in a fixed order; squared norms are formed without fused multiply-adds so they
+// equal the textbook formula term by term.
+#include <hip/hip_cooperative_groups.h>
+
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "internal.h"
 
+namespace cg = cooperative_groups;
+
 namespace rbf {
 namespace {
 
-constexpr int UPB = 64;       // surface points per update workgroup (one per lane)
-constexpr int UWAVES = 4;     // waves per update workgroup, each a slice of the dot product
+constexpr int UPB = 64;       // surface points per tile (one per lane)
+constexpr int UWAVES = 4;     // waves per workgroup, each a slice of the dot product
+constexpr int NT = UPB * UWAVES;
 constexpr int LCHUNK = 2048;  // Newton row entries staged per LDS pass
 
 struct GState {
@@ -46,6 +55,40 @@ struct GState {
 struct Cand {
     double m2;
     int64_t idx;
+};
+
+struct GArgs {
+    GState *st;
+    const double *xs;
+    int64_t n_s;
+    double R;
+    double *V;           // [cols][n_s] column-major Newton basis
+    double *Lpack;       // packed lower factor, row n at n (n + 1) / 2
+    double *coef;        // [DIM][ld_coef] Newton coefficients y
+    int64_t ld_coef;
+    double *E;           // [DIM][n_s] current error
+    uint8_t *sel;        // [n_s] selected in this level
+    Cand *part;          // [g] per-tile maxima
+    int64_t g;           // number of tiles
+    int64_t *ctrl;       // this level's slice of the output control list
+    double *hist;
+    int64_t hist_cap;
+    int64_t cap_level;
+    const int64_t *seeds;  // device [n_seeds]
+    int64_t n_seeds;
+    int64_t max_iter;
+};
+
+struct SelShared {
+    Cand sh[UWAVES];
+    double red[NT];
+    int32_t stop, skip;
+    int64_t n;
+};
+
+struct UpdShared {
+    double lsh[LCHUNK];
+    double psum[UWAVES][UPB];
 };
 
 __device__ __forceinline__ bool better(double m2, int64_t i, double bm2, int64_t bi)
@@ -66,8 +109,8 @@ __device__ __forceinline__ double norm2_plain(const double *v, int64_t ld, int64
     return s;
 }
 
-// phi(||a - b|| / R) term by term as the textbook formula (no contraction), for the few basis
-// values computed per iteration.
+// phi(||x_i - x_j|| / R) term by term as the textbook formula (no contraction); only a few of
+// these are computed per iteration.
 template <int DIM>
 __device__ __forceinline__ double phi_pair(const double *xs, int64_t ld, int64_t i, int64_t j, double R)
 {
@@ -96,7 +139,7 @@ __device__ __forceinline__ void wave_argmax(double &m2, int64_t &idx)
     }
 }
 
-// E = r, selected = 0, per-block max of ||r_i||^2 (no exclusions).
+// E = r, selected = 0, per-tile max of ||r_i||^2 (no exclusions).
 template <int DIM>
 __global__ __launch_bounds__(64) void g_init(const double *r, double *E, uint8_t *sel, int64_t n_s,
                                              Cand *part)
@@ -115,11 +158,12 @@ __global__ __launch_bounds__(64) void g_init(const double *r, double *E, uint8_t
     if (threadIdx.x == 0) part[blockIdx.x] = Cand{m2, idx};
 }
 
+// Fixed-order reduction of the per-tile maxima by one workgroup of NT threads.
 __device__ void block_argmax(const Cand *part, int64_t g, double &m2, int64_t &idx, Cand *sh)
 {
     double bm = -1.0;
     int64_t bi = -1;
-    for (int64_t b = threadIdx.x; b < g; b += blockDim.x) {
+    for (int64_t b = threadIdx.x; b < g; b += NT) {
         Cand c = part[b];
         if (better(c.m2, c.idx, bm, bi)) {
             bm = c.m2;
@@ -127,11 +171,11 @@ __device__ void block_argmax(const Cand *part, int64_t g, double &m2, int64_t &i
         }
     }
     wave_argmax(bm, bi);
-    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0) sh[w] = Cand{bm, bi};
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int k = 1; k < (int)(blockDim.x >> 6); ++k)
+        for (int k = 1; k < UWAVES; ++k)
             if (better(sh[k].m2, sh[k].idx, bm, bi)) {
                 bm = sh[k].m2;
                 bi = sh[k].idx;
@@ -141,13 +185,14 @@ __device__ void block_argmax(const Cand *part, int64_t g, double &m2, int64_t &i
     __syncthreads();
     m2 = sh[0].m2;
     idx = sh[0].idx;
+    __syncthreads();
 }
 
-// Level start: the level target from max ||r||^2, as max(eps, rho * max ||r||) squared.
-__global__ __launch_bounds__(256) void g_begin(GState *st, const Cand *part, int64_t g, double eps,
-                                               double rho, int32_t last)
+// Level start: the level target max(eps, rho * max ||r||), squared.
+__global__ __launch_bounds__(NT) void g_begin(GState *st, const Cand *part, int64_t g, double eps,
+                                              double rho, int32_t last)
 {
-    __shared__ Cand sh[4];
+    __shared__ Cand sh[UWAVES];
     double m2;
     int64_t idx;
     block_argmax(part, g, m2, idx, sh);
@@ -163,148 +208,260 @@ __global__ __launch_bounds__(256) void g_begin(GState *st, const Cand *part, int
     }
 }
 
-// One selection: argmax (or a forced seed), stop tests, Newton row extraction and pivot.
+// Select phase (one workgroup): finish the pending column, choose the next point (argmax or a
+// forced seed), apply the stop tests, extract the Newton row l = V[p, 0:n] as row n of the
+// Cholesky factor and form the pivot d = sqrt(phi(0) - l.l) and the coefficients y_n = E_p / d.
 template <int DIM>
-__global__ __launch_bounds__(256) void g_select(GState *st, const Cand *part, int64_t g,
-                                                int64_t forced, int64_t cap_level, const double *V,
-                                                int64_t ldV, double *Lpack, double *coef,
-                                                int64_t ld_coef, const double *E, int64_t n_s,
-                                                int64_t *ctrl, uint8_t *sel, double *hist,
-                                                int64_t hist_cap)
+__device__ void select_phase(const GArgs &a, int64_t forced, SelShared &s)
 {
-    __shared__ Cand sh[4];
-    __shared__ double red[256];
-    __shared__ int32_t s_stop, s_skip;
-    __shared__ int64_t s_n;
+    GState *st = a.st;
     if (threadIdx.x == 0) {
-        s_skip = st->stop >= 0;            // level already finished
-        if (!s_skip && st->go) {           // the previous update completed column n
+        s.skip = st->stop >= 0;            // level already finished
+        if (!s.skip && st->go) {           // the previous update completed column n
             st->n += 1;
             st->go = 0;
         }
-        s_n = st->n;
+        s.n = st->n;
     }
     __syncthreads();
-    if (s_skip) return;
-    const int64_t n = s_n;
+    if (s.skip) return;
+    const int64_t n = s.n;
     double m2 = 0.0;
     int64_t p = forced;
-    if (forced < 0) block_argmax(part, g, m2, p, sh);
+    if (forced < 0) block_argmax(a.part, a.g, m2, p, s.sh);
     if (threadIdx.x == 0) {
         int32_t stop = -1;
         if (forced < 0) {
             if (p < 0) stop = RBF_STOP_ALL_SELECTED;
             else if (m2 < st->target2) stop = RBF_STOP_EPS;
         }
-        if (stop < 0 && n >= cap_level) stop = RBF_STOP_CAP;
-        s_stop = stop;
+        if (stop < 0 && n >= a.cap_level) stop = RBF_STOP_CAP;
+        s.stop = stop;
         if (stop >= 0) st->stop = stop;
     }
     __syncthreads();
-    if (s_stop >= 0) return;
+    if (s.stop >= 0) return;
 
-    // l = V[p, 0:n] is the new row of the Cholesky factor of Phi_cc.
-    double *row = Lpack + (n * (n + 1)) / 2;
+    double *row = a.Lpack + (n * (n + 1)) / 2;
     double part_ll = 0.0;
-    for (int64_t j = threadIdx.x; j < n; j += blockDim.x) {
-        double v = V[j * ldV + p];
+    for (int64_t j = threadIdx.x; j < n; j += NT) {
+        const double v = a.V[j * a.n_s + p];
         row[j] = v;
         part_ll = __builtin_fma(v, v, part_ll);
     }
-    red[threadIdx.x] = part_ll;
+    s.red[threadIdx.x] = part_ll;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int k = NT / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) s.red[threadIdx.x] += s.red[threadIdx.x + k];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        double d2 = 1.0 - red[0];     // phi(0) - l.l
+        const double d2 = 1.0 - s.red[0];     // phi(0) - l.l
         // l.l carries about (n + 1) ulps of rounding: a pivot below that is zero (breakdown).
         if (!(d2 > (double)(n + 1) * 0x1p-52)) {
             st->stop = RBF_STOP_BREAKDOWN;
-            return;
-        }
-        double d = sqrt(d2);
-        row[n] = d;
-        st->p = p;
-        st->d = d;
+        } else {
+            const double d = sqrt(d2);
+            row[n] = d;
+            st->p = p;
+            st->d = d;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            double c = E[k * n_s + p] / d;
-            st->c[k] = c;
-            coef[k * ld_coef + n] = c;
+            for (int k = 0; k < DIM; ++k) {
+                const double c = a.E[k * a.n_s + p] / d;
+                st->c[k] = c;
+                a.coef[k * a.ld_coef + n] = c;
+            }
+            a.ctrl[n] = p;
+            a.sel[p] = 1;
+            if (forced < 0) {
+                if (st->n_iter < a.hist_cap) a.hist[st->n_iter] = sqrt(m2);
+                st->n_iter += 1;
+            }
+            st->go = 1;
         }
-        ctrl[n] = p;
-        sel[p] = 1;
-        if (forced < 0) {
-            if (st->n_iter < hist_cap) hist[st->n_iter] = sqrt(m2);
-            st->n_iter += 1;
-        }
-        st->go = 1;
     }
+    __syncthreads();
 }
 
-// New Newton column, error update and per-block argmax. Lane = surface point, wave = slice of
-// the dot product V[i, 0:n] . l.
+// Update phase for one tile of 64 surface points: lane = point, wave = slice of the dot product
+// V[i, 0:n] . l. Writes column n, updates E and the tile's argmax of ||E_i||^2 over unselected i.
 template <int DIM>
-__global__ __launch_bounds__(UPB *UWAVES) void g_update(const GState *st, const double *xs,
-                                                        int64_t n_s, double R, double *V,
-                                                        int64_t ldV, const double *Lpack,
-                                                        double *E, const uint8_t *sel, Cand *part)
+__device__ void update_tile(const GArgs &a, int64_t tile, int64_t n, int64_t p, double d,
+                            const double (&c)[DIM], UpdShared &u)
 {
-    __shared__ double lsh[LCHUNK];
-    __shared__ double psum[UWAVES][UPB];
-    if (!st->go) return;
-    const int64_t n = st->n;
-    const int64_t p = st->p;
-    const double *lrow = Lpack + (n * (n + 1)) / 2;
+    const double *lrow = a.Lpack + (n * (n + 1)) / 2;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t i = (int64_t)blockIdx.x * UPB + lane;
-    const bool ok = i < n_s;
+    const int64_t i = tile * UPB + lane;
+    const bool ok = i < a.n_s;
     const int64_t ic = ok ? i : 0;
+    const int64_t ldV = a.n_s;
 
     double s = 0.0;
     for (int64_t j0 = 0; j0 < n; j0 += LCHUNK) {
         const int nj = (int)min<int64_t>(LCHUNK, n - j0);
         __syncthreads();
-        for (int t = threadIdx.x; t < nj; t += UPB * UWAVES) lsh[t] = lrow[j0 + t];
+        for (int t = threadIdx.x; t < nj; t += NT) u.lsh[t] = lrow[j0 + t];
         __syncthreads();
         const int per = (nj + UWAVES - 1) / UWAVES;
         const int jb = w * per, je = min(nj, jb + per);
-        const double *col = V + (j0 + jb) * ldV + ic;
+        const double *col = a.V + (j0 + jb) * ldV + ic;
         int j = jb;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         for (; j + 4 <= je; j += 4, col += 4 * ldV) {
-            s0 = __builtin_fma(col[0], lsh[j], s0);
-            s1 = __builtin_fma(col[ldV], lsh[j + 1], s1);
-            s2 = __builtin_fma(col[2 * ldV], lsh[j + 2], s2);
-            s3 = __builtin_fma(col[3 * ldV], lsh[j + 3], s3);
+            s0 = __builtin_fma(col[0], u.lsh[j], s0);
+            s1 = __builtin_fma(col[ldV], u.lsh[j + 1], s1);
+            s2 = __builtin_fma(col[2 * ldV], u.lsh[j + 2], s2);
+            s3 = __builtin_fma(col[3 * ldV], u.lsh[j + 3], s3);
         }
-        for (; j < je; ++j, col += ldV) s0 = __builtin_fma(col[0], lsh[j], s0);
+        for (; j < je; ++j, col += ldV) s0 = __builtin_fma(col[0], u.lsh[j], s0);
         s += (s0 + s1) + (s2 + s3);
     }
-    psum[w][lane] = s;
+    u.psum[w][lane] = s;
     __syncthreads();
-    if (w != 0) return;
-
-    double m2 = -1.0;
-    int64_t idx = -1;
-    if (ok) {
-        double dot = psum[0][lane];
+    if (w == 0) {
+        double m2 = -1.0;
+        int64_t idx = -1;
+        if (ok) {
+            double dot = u.psum[0][lane];
 #pragma unroll
-        for (int k = 1; k < UWAVES; ++k) dot += psum[k][lane];
-        const double d = st->d;
-        double v = (phi_pair<DIM>(xs, n_s, i, p, R) - dot) / d;
-        V[n * ldV + i] = v;
+            for (int k = 1; k < UWAVES; ++k) dot += u.psum[k][lane];
+            const double v = (phi_pair<DIM>(a.xs, a.n_s, i, p, a.R) - dot) / d;
+            a.V[n * ldV + i] = v;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) E[k * n_s + i] = __builtin_fma(-st->c[k], v, E[k * n_s + i]);
-        if (!sel[i]) {
-            m2 = norm2_plain<DIM>(E, n_s, i);
-            idx = i;
+            for (int k = 0; k < DIM; ++k) a.E[k * a.n_s + i] = __builtin_fma(-c[k], v, a.E[k * a.n_s + i]);
+            if (!a.sel[i]) {
+                m2 = norm2_plain<DIM>(a.E, a.n_s, i);
+                idx = i;
+            }
         }
+        wave_argmax(m2, idx);
+        if (lane == 0) a.part[tile] = Cand{m2, idx};
     }
-    wave_argmax(m2, idx);
-    if (lane == 0) part[blockIdx.x] = Cand{m2, idx};
+    __syncthreads();
+}
+
+// ---- two-kernel form (fallback) -------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(NT) void g_select(GArgs a, int64_t forced)
+{
+    __shared__ SelShared s;
+    select_phase<DIM>(a, forced, s);
+}
+
+template <int DIM>
+__global__ __launch_bounds__(NT) void g_update(GArgs a)
+{
+    __shared__ UpdShared u;
+    const GState *st = a.st;
+    if (!st->go) return;
+    double c[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) c[k] = st->c[k];
+    update_tile<DIM>(a, blockIdx.x, st->n, st->p, st->d, c, u);
+}
+
+// ---- persistent cooperative form ----------------------------------------------------------------
+// Every workgroup runs the same iteration count: the loop ends when the state read after a grid
+// barrier says the level stopped (or after max_iter iterations, a bound the level can never
+// legitimately reach), so all workgroups leave together.
+template <int DIM>
+__global__ __launch_bounds__(NT) void g_level(GArgs a)
+{
+    __shared__ SelShared s;
+    __shared__ UpdShared u;
+    __shared__ int32_t go_sh;
+    __shared__ int64_t n_sh, p_sh;
+    __shared__ double d_sh, c_sh[3];
+    cg::grid_group grid = cg::this_grid();
+    for (int64_t it = 0; it < a.max_iter; ++it) {
+        if (blockIdx.x == 0) select_phase<DIM>(a, it < a.n_seeds ? a.seeds[it] : -1, s);
+        grid.sync();
+        if (threadIdx.x == 0) {
+            const GState *st = a.st;
+            go_sh = st->go;
+            n_sh = st->n;
+            p_sh = st->p;
+            d_sh = st->d;
+            for (int k = 0; k < DIM; ++k) c_sh[k] = st->c[k];
+        }
+        __syncthreads();
+        if (!go_sh) break;
+        double c[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) c[k] = c_sh[k];
+        const int64_t n = n_sh, p = p_sh;
+        const double d = d_sh;
+        for (int64_t t = blockIdx.x; t < a.g; t += gridDim.x) update_tile<DIM>(a, t, n, p, d, c, u);
+        grid.sync();
+    }
+}
+
+// ---- persistent form with one barrier per iteration ------------------------------------------
+// Generation barrier in device memory (zeroed before launch). The last workgroup to arrive runs
+// the select phase for the next iteration before it releases the others, so an iteration costs
+// one arrival/release instead of two full barriers. Every workgroup executes the same number of
+// barriers: the exit test reads the state published by the release.
+struct GridBar {
+    unsigned int count;
+    unsigned int gen;
+};
+
+template <int DIM>
+__global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
+{
+    __shared__ SelShared s;
+    __shared__ UpdShared u;
+    __shared__ int32_t go_sh, last_sh;
+    __shared__ int64_t n_sh, p_sh;
+    __shared__ double d_sh, c_sh[3];
+    const unsigned int nb = gridDim.x;
+    for (int64_t it = 0; it < a.max_iter; ++it) {
+        if (it > 0) {
+            for (int64_t t = blockIdx.x; t < a.g; t += nb) {
+                double c[DIM];
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) c[k] = c_sh[k];
+                update_tile<DIM>(a, t, n_sh, p_sh, d_sh, c, u);
+            }
+        }
+        // Arrive: the workgroup barrier orders this workgroup's stores, one release by thread 0
+        // publishes them device-wide. The last arriver acquires, selects, then releases the
+        // others, which poll the generation with relaxed loads and acquire once.
+        __syncthreads();
+        unsigned int g0 = 0;
+        if (threadIdx.x == 0) {
+            g0 = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned int arrived =
+                __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            last_sh = arrived == nb - 1;
+            if (last_sh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (last_sh) {
+            const int64_t k = it;   // selection number within the level (seeds first)
+            select_phase<DIM>(a, k < a.n_seeds ? a.seeds[k] : -1, s);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else if (threadIdx.x == 0) {
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0)
+                __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const GState *st = a.st;
+            go_sh = __hip_atomic_load(&st->go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            n_sh = st->n;
+            p_sh = st->p;
+            d_sh = st->d;
+            for (int k = 0; k < DIM; ++k) c_sh[k] = st->c[k];
+        }
+        __syncthreads();
+        if (!go_sh) break;
+    }
 }
 
 // Blocked back substitution L^T alpha = y for the 64 rows [b0, b1) (all later rows done).
@@ -315,10 +472,11 @@ __global__ __launch_bounds__(256) void g_backsolve(const double *Lpack, double *
                                                    double *alpha, int64_t ld_a, int64_t b0, int64_t b1)
 {
     __shared__ double Lb[64][65];
+    __shared__ double inv[64];
     __shared__ double xb[DIM][64];
     const int nb = (int)(b1 - b0);
     for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x) {
-        int r = t / 64, c = t % 64;
+        const int r = t / 64, c = t % 64;
         Lb[r][c] = (r < nb && c <= r) ? Lpack[((b0 + r) * (b0 + r + 1)) / 2 + b0 + c] : 0.0;
     }
     if (threadIdx.x < 64) {
@@ -328,21 +486,19 @@ __global__ __launch_bounds__(256) void g_backsolve(const double *Lpack, double *
     __syncthreads();
     if (threadIdx.x < 64) {
         const int j = threadIdx.x;
+        inv[j] = j < nb ? 1.0 / Lb[j][j] : 0.0;
         double rhs[DIM];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) rhs[k] = xb[k][j];
         for (int i = nb - 1; i >= 0; --i) {
+            const double ii = inv[i];
             double xi[DIM];
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                double v = rhs[k] / Lb[i][i];
-                xi[k] = __shfl(v, i, 64);
-            }
+            for (int k = 0; k < DIM; ++k) xi[k] = __shfl(rhs[k], i, 64) * ii;
             if (j < i) {
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[i][j], xi[k], rhs[k]);
-            }
-            if (j == i) {
+            } else if (j == i) {
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) rhs[k] = xi[k];
             }
@@ -362,7 +518,7 @@ __global__ __launch_bounds__(256) void g_backsolve(const double *Lpack, double *
 #pragma unroll
         for (int k = 0; k < DIM; ++k) acc[k] = 0.0;
         for (int i = 0; i < nb; ++i) {
-            double lij = Lpack[((b0 + i) * (b0 + i + 1)) / 2 + jj];
+            const double lij = Lpack[((b0 + i) * (b0 + i + 1)) / 2 + jj];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) acc[k] = __builtin_fma(lij, xb[k][i], acc[k]);
         }
@@ -377,7 +533,7 @@ __global__ __launch_bounds__(256) void g_gather(const double *xs, int64_t n_s, c
 {
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * blockDim.x) {
-        int64_t p = ctrl[j];
+        const int64_t p = ctrl[j];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) xc[k * ld + j] = xs[k * n_s + p];
     }
@@ -390,6 +546,16 @@ __global__ void g_finite(const double *a, int64_t n, int32_t *bad)
         if (!isfinite(a[i])) *bad = 1;
 }
 
+int cooperative_blocks(const void *kernel, int n_cu)
+{
+    int dev = 0, coop = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, NT, 0) != hipSuccess) return 0;
+    return per_cu * n_cu;
+}
+
 template <int DIM>
 rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, const double *xs,
                        const double *ds, rbf_ctrl_set *out, hipStream_t s)
@@ -399,7 +565,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     const int64_t cols = std::min<int64_t>(n_s, cap);      // most columns one level can need
     const int64_t g = (n_s + UPB - 1) / UPB;
 
-    DevBuf bV, bL, bE, bR, bR2, bSel, bPart, bState, bCoef, bHist, bFlag;
+    DevBuf bV, bL, bE, bR, bR2, bSel, bPart, bState, bCoef, bHist, bFlag, bSeeds;
     RBF_TRY(bV.get(pool, sizeof(double) * (size_t)cols * (size_t)n_s));
     RBF_TRY(bL.get(pool, sizeof(double) * (size_t)(cols * (cols + 1) / 2 + 1)));
     RBF_TRY(bE.get(pool, sizeof(double) * DIM * (size_t)n_s));
@@ -411,10 +577,9 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     RBF_TRY(bCoef.get(pool, sizeof(double) * DIM * (size_t)cols));
     RBF_TRY(bHist.get(pool, sizeof(double) * (size_t)cap));
     RBF_TRY(bFlag.get(pool, sizeof(int32_t)));
-    double *V = bV.as<double>(), *Lp = bL.as<double>(), *E = bE.as<double>();
-    double *R = bR.as<double>(), *R2 = bR2.as<double>(), *coef = bCoef.as<double>();
-    uint8_t *sel = bSel.as<uint8_t>();
-    Cand *part = bPart.as<Cand>();
+    const int32_t n_seed_total = prm.seed_off ? prm.seed_off[prm.n_levels] : 1;
+    RBF_TRY(bSeeds.get(pool, sizeof(int64_t) * (size_t)std::max(1, n_seed_total)));
+    double *R = bR.as<double>(), *R2 = bR2.as<double>();
     GState *st = bState.as<GState>();
 
     // Reject non-finite coordinates or displacements.
@@ -426,11 +591,49 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     RBF_HIP(hipStreamSynchronize(s));
     if (bad) return fail(RBF_E_INVALID, "xs or ds holds a non-finite value");
 
+    // Seeds of every level (paper default: the first surface point at level 0).
+    std::vector<int64_t> seeds_h;
+    std::vector<int32_t> seed_off(prm.n_levels + 1, 0);
+    if (prm.seed_off) {
+        for (int l = 0; l <= prm.n_levels; ++l) seed_off[l] = prm.seed_off[l];
+        seeds_h.assign(prm.seed_idx, prm.seed_idx + prm.seed_off[prm.n_levels]);
+    } else {
+        seeds_h.push_back(0);
+        for (int l = 1; l <= prm.n_levels; ++l) seed_off[l] = 1;
+    }
+    if (!seeds_h.empty())
+        RBF_HIP(hipMemcpyAsync(bSeeds.ptr, seeds_h.data(), sizeof(int64_t) * seeds_h.size(),
+                               hipMemcpyHostToDevice, s));
     RBF_HIP(hipMemsetAsync(st, 0, sizeof(GState), s));
     RBF_HIP(hipMemcpyAsync(R, ds, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
 
+    // Execution mode: "lean" (one barrier per iteration, default), "cg" (cooperative-groups grid
+    // barriers) or "kernels" (two launches per iteration).
+    const char *mode_env = getenv("RBF_GREEDY_MODE");
+    const int mode = getenv("RBF_NO_COOP") ? 2 : (mode_env && !strcmp(mode_env, "cg")) ? 1
+                   : (mode_env && !strcmp(mode_env, "kernels")) ? 2 : 0;
+    const int coop_max = mode == 2 ? 0
+                       : cooperative_blocks(mode == 0 ? (const void *)g_level_lean<DIM> : (const void *)g_level<DIM>,
+                                            ctx->n_cu);
+    DevBuf bBar;
+    RBF_TRY(bBar.get(pool, sizeof(GridBar)));
+    GArgs a{};
+    a.st = st;
+    a.xs = xs;
+    a.n_s = n_s;
+    a.V = bV.as<double>();
+    a.Lpack = bL.as<double>();
+    a.coef = bCoef.as<double>();
+    a.ld_coef = cols;
+    a.E = bE.as<double>();
+    a.sel = bSel.as<uint8_t>();
+    a.part = bPart.as<Cand>();
+    a.g = g;
+    a.hist = bHist.as<double>();
+    a.hist_cap = cap;
+
     GState hs{};
-    int64_t total = 0, iters_before = 0;
+    int64_t total = 0;
     int used = 0;
     out->level_off[0] = 0;
     for (int l = 0; l < RBF_MAX_LEVELS; ++l) {
@@ -439,54 +642,78 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     }
     for (int l = 0; l < prm.n_levels; ++l) {
         const double Rl = prm.radius[l];
-        const int64_t cap_level = std::min<int64_t>(cols, cap - total);
-        hipLaunchKernelGGL(g_init<DIM>, dim3((unsigned)g), dim3(64), 0, s, R, E, sel, n_s, part);
-        hipLaunchKernelGGL(g_begin, dim3(1), dim3(256), 0, s, st, part, g, prm.eps_abs,
+        a.R = Rl;
+        a.cap_level = std::min<int64_t>(cols, cap - total);
+        a.ctrl = out->ctrl_idx + total;
+        a.seeds = bSeeds.as<int64_t>() + seed_off[l];
+        a.n_seeds = seed_off[l + 1] - seed_off[l];
+        a.max_iter = a.n_seeds + a.cap_level + 2;
+        hipLaunchKernelGGL(g_init<DIM>, dim3((unsigned)g), dim3(64), 0, s, R, a.E, a.sel, n_s, a.part);
+        hipLaunchKernelGGL(g_begin, dim3(1), dim3(NT), 0, s, st, a.part, g, prm.eps_abs,
                            prm.level_reduction, (int32_t)(l == prm.n_levels - 1));
-        int64_t *ctrl = out->ctrl_idx + total;
-        auto step = [&](int64_t forced) {
-            hipLaunchKernelGGL(g_select<DIM>, dim3(1), dim3(256), 0, s, st, part, g, forced, cap_level,
-                               V, n_s, Lp, coef, cols, E, n_s, ctrl, sel, bHist.as<double>(), cap);
-            hipLaunchKernelGGL(g_update<DIM>, dim3((unsigned)g), dim3(UPB * UWAVES), 0, s, st, xs, n_s,
-                               Rl, V, n_s, Lp, E, sel, part);
-        };
-        if (prm.seed_off) {
-            for (int32_t k = prm.seed_off[l]; k < prm.seed_off[l + 1]; ++k) step(prm.seed_idx[k]);
-        } else if (l == 0) {
-            step(0);
-        }
         RBF_HIP(hipGetLastError());
-        // Argmax iterations in batches; the device stops itself, extra launches are no-ops.
-        // Every effective iteration adds a column, so the level ends within cap_level + 1
-        // selections; the host gives up (device error) well after that.
-        int64_t batch = 16, launched = 0;
-        for (;;) {
-            for (int64_t b = 0; b < batch; ++b) step(-1);
-            launched += batch;
-            RBF_HIP(hipGetLastError());
-            RBF_HIP(hipMemcpyAsync(&hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
-            RBF_HIP(hipStreamSynchronize(s));
-            if (hs.stop >= 0) break;
-            if (launched > cap_level + 1024)
-                return fail(RBF_E_DEVICE, "greedy level %d did not terminate after %lld selections", l,
-                            (long long)launched);
-            batch = std::min<int64_t>(batch * 2, 256);
+        bool done = false;
+        if (coop_max > 0) {
+            const unsigned G = (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, coop_max));
+            hipError_t e;
+            if (mode == 0) {
+                RBF_HIP(hipMemsetAsync(bBar.ptr, 0, sizeof(GridBar), s));
+                GridBar *barp = bBar.as<GridBar>();
+                void *args[] = {&a, &barp};
+                e = hipLaunchCooperativeKernel((const void *)g_level_lean<DIM>, dim3(G), dim3(NT), args, 0, s);
+            } else {
+                void *args[] = {&a};
+                e = hipLaunchCooperativeKernel((const void *)g_level<DIM>, dim3(G), dim3(NT), args, 0, s);
+            }
+            if (e == hipSuccess) {
+                RBF_HIP(hipMemcpyAsync(&hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
+                RBF_HIP(hipStreamSynchronize(s));
+                if (hs.stop < 0)
+                    return fail(RBF_E_DEVICE, "greedy level %d did not stop within %lld iterations", l,
+                                (long long)a.max_iter);
+                done = true;
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        if (!done) {
+            // Two kernels per iteration; the device stops itself and later launches are no-ops.
+            for (int64_t k = 0; k < a.n_seeds; ++k) {
+                hipLaunchKernelGGL(g_select<DIM>, dim3(1), dim3(NT), 0, s, a, seeds_h[seed_off[l] + k]);
+                hipLaunchKernelGGL(g_update<DIM>, dim3((unsigned)g), dim3(NT), 0, s, a);
+            }
+            int64_t batch = 16, launched = 0;
+            for (;;) {
+                for (int64_t b = 0; b < batch; ++b) {
+                    hipLaunchKernelGGL(g_select<DIM>, dim3(1), dim3(NT), 0, s, a, (int64_t)-1);
+                    hipLaunchKernelGGL(g_update<DIM>, dim3((unsigned)g), dim3(NT), 0, s, a);
+                }
+                launched += batch;
+                RBF_HIP(hipGetLastError());
+                RBF_HIP(hipMemcpyAsync(&hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
+                RBF_HIP(hipStreamSynchronize(s));
+                if (hs.stop >= 0) break;
+                if (launched > a.cap_level + 1024)
+                    return fail(RBF_E_DEVICE, "greedy level %d did not stop after %lld selections", l,
+                                (long long)launched);
+                batch = std::min<int64_t>(batch * 2, 256);
+            }
         }
         const int64_t n = hs.n;
         out->level_stop[l] = hs.stop;
         // Weights: L^T alpha = y, blocked from the bottom.
         double *alpha = out->alpha + total;
         if (n > 0) {
-            RBF_HIP(hipMemcpy2DAsync(R2, sizeof(double) * cols, coef, sizeof(double) * cols,
+            RBF_HIP(hipMemcpy2DAsync(R2, sizeof(double) * cols, a.coef, sizeof(double) * cols,
                                      sizeof(double) * n, DIM, hipMemcpyDeviceToDevice, s));
             for (int64_t b1 = n; b1 > 0; b1 -= 64) {
-                int64_t b0 = std::max<int64_t>(0, b1 - 64);
-                unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b0 + 255) / 256, 1024));
-                hipLaunchKernelGGL(g_backsolve<DIM>, dim3(gb), dim3(256), 0, s, Lp, R2, cols, alpha,
+                const int64_t b0 = std::max<int64_t>(0, b1 - 64);
+                const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b0 + 255) / 256, 1024));
+                hipLaunchKernelGGL(g_backsolve<DIM>, dim3(gb), dim3(256), 0, s, a.Lpack, R2, cols, alpha,
                                    out->capacity, b0, b1);
             }
-            unsigned gg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
-            hipLaunchKernelGGL(g_gather<DIM>, dim3(gg), dim3(256), 0, s, xs, n_s, ctrl, n,
+            const unsigned gg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
+            hipLaunchKernelGGL(g_gather<DIM>, dim3(gg), dim3(256), 0, s, xs, n_s, a.ctrl, n,
                                out->xc + total, out->capacity);
             RBF_HIP(hipGetLastError());
             // dS_{l+1} = dS_l - Phi_sC alpha at every surface point, FP64 kernel sum.
@@ -510,8 +737,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         out->level_off[l + 1] = (int32_t)total;
         used = l + 1;
         // max ||dS_{l+1}|| decides whether another level is needed.
-        hipLaunchKernelGGL(g_init<DIM>, dim3((unsigned)g), dim3(64), 0, s, R, E, sel, n_s, part);
-        hipLaunchKernelGGL(g_begin, dim3(1), dim3(256), 0, s, st, part, g, prm.eps_abs,
+        hipLaunchKernelGGL(g_init<DIM>, dim3((unsigned)g), dim3(64), 0, s, R, a.E, a.sel, n_s, a.part);
+        hipLaunchKernelGGL(g_begin, dim3(1), dim3(NT), 0, s, st, a.part, g, prm.eps_abs,
                            prm.level_reduction, 1);
         RBF_HIP(hipGetLastError());
         RBF_HIP(hipMemcpyAsync(&hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
@@ -522,7 +749,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     for (int l = used; l < prm.n_levels; ++l) out->level_off[l + 1] = (int32_t)total;
     out->n_levels_used = used;
     out->stop_reason = out->level_stop[used - 1];
-    out->n_iterations = hs.n_iter - iters_before;
+    out->n_iterations = hs.n_iter;
     if (out->e_final)
         RBF_HIP(hipMemcpyAsync(out->e_final, R, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
     RBF_HIP(hipStreamSynchronize(s));
