@@ -546,6 +546,26 @@ __global__ void g_finite(const double *a, int64_t n, int32_t *bad)
         if (!isfinite(a[i])) *bad = 1;
 }
 
+// Holds G workgroups of the context's co-residency budget while a persistent kernel runs.
+struct CoopTicket {
+    rbf_ctx ctx;
+    int64_t units;
+    CoopTicket(rbf_ctx c, int64_t g, int64_t cap) : ctx(c), units(g)
+    {
+        std::unique_lock<std::mutex> lk(ctx->coop_mu);
+        ctx->coop_cv.wait(lk, [&] { return ctx->coop_in_use + units <= cap; });
+        ctx->coop_in_use += units;
+    }
+    ~CoopTicket()
+    {
+        {
+            std::lock_guard<std::mutex> lk(ctx->coop_mu);
+            ctx->coop_in_use -= units;
+        }
+        ctx->coop_cv.notify_all();
+    }
+};
+
 int cooperative_blocks(const void *kernel, int n_cu)
 {
     int dev = 0, coop = 0, per_cu = 0;
@@ -655,6 +675,9 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         bool done = false;
         if (coop_max > 0) {
             const unsigned G = (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, coop_max));
+            // Persistent kernels of concurrent requests must fit on the device together, or their
+            // spinning workgroups could wait for each other's unscheduled ones.
+            CoopTicket gate(ctx, G, coop_max);
             hipError_t e;
             if (mode == 0) {
                 RBF_HIP(hipMemsetAsync(bBar.ptr, 0, sizeof(GridBar), s));

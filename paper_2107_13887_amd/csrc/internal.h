@@ -94,10 +94,14 @@ class Server;   // serving loop (serve.cpp)
 struct Geometry {
     int32_t dim = 0;
     int64_t n_s = 0, n_v = 0;
-    DevBuf xs, xv_sorted, d_sorted, perm;   // volume sorted by wall distance, perm: sorted -> orig
+    DevBuf xs, xv_sorted, d_sorted, perm;   // volume in wall-distance order, perm: stored -> caller
+    std::vector<int32_t> bin_off;           // host: start of each wall-distance bin, plus n_v
+    uint64_t lo_bits = 0;                   // bin(d) = (bits(d) - lo_bits) >> shift
+    int shift = 0;
     // Control sets of the last finished request (warm start), host copies per level.
     std::vector<std::vector<int64_t>> last_ctrl;
-    int32_t refs = 0;
+    int32_t refs = 0;        // queued or running requests (guarded by the server's lock)
+    bool running = false;    // a request on this geometry is running
     uint64_t bytes = 0;
 };
 
@@ -126,6 +130,10 @@ struct rbf_ctx_s {
     std::mutex geom_mu;
     std::unordered_map<rbf_geom, std::unique_ptr<rbf::Geometry>> geoms;
     int n_cu = 256;
+    // Co-residency budget of the persistent greedy kernels running at once (workgroups).
+    std::mutex coop_mu;
+    std::condition_variable coop_cv;
+    int64_t coop_in_use = 0;
 };
 
 struct rbf_geom_s {};  // opaque handle; the address keys the context's geometry table
@@ -154,7 +162,11 @@ struct SumProblem {
     double sign = -1.0;
     double *out = nullptr;        // [dim][n_p], fully written
     int32_t precision = RBF_FP64;
-    bool sorted_by_d = false;     // dwall ascending: the reduced volume is a prefix
+    // Resident geometry: points (xp, dwall) are stored in wall-distance order, the reduced volume
+    // is the prefix [0, n_active), and result v goes to out[.][perm[v]] (perm: stored -> caller
+    // order); points beyond the prefix get +0.0 through perm. n_active < 0: not used.
+    const int32_t *perm = nullptr;
+    int64_t n_active = -1;
 };
 
 // Enqueues the whole evaluation on `s`; scratch comes from the pool and is released

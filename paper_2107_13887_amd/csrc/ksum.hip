@@ -11,9 +11,9 @@
 //     same LDS address, a broadcast without bank conflicts;
 //   * the control list of each level may be split over gridDim.y so that few points still give
 //     enough waves; split partial sums are reduced in a fixed order (deterministic results);
-//   * the wall-distance reduction keeps only points with d < max_l D_l: the prefix of a volume
-//     sorted by d, or a one-pass compaction that also writes +0.0 to every dropped point (the
-//     order of the compacted list does not affect any result: each point's sum is independent);
+//   * the wall-distance reduction keeps only points with d < max_l D_l: the prefix of a resident
+//     volume stored in wall-distance order, or a stable two-kernel compaction that also writes
+//     +0.0 to every dropped point;
 //   * FP64 square root from the hardware reciprocal square-root estimate e refined by one
 //     Goldschmidt step (error ~1.5 e^2) and one Newton correction (error ~1.5 e^3);
 //   * mixed precision: the pair arithmetic runs in FP32 on coordinates shifted to a per-workgroup
@@ -34,6 +34,7 @@ struct KArgs {
     const double *alpha;            // [DIM][ld_ctrl]
     int64_t ld_ctrl;
     const int32_t *work;            // reduced point list, or null for the identity
+    const int32_t *out_perm;        // resident geometry: output index of stored point w
     const int64_t *n_work_dev;      // device-side count (null: use n_work)
     int64_t n_work;
     const double *xp;
@@ -222,9 +223,10 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
     for (int p = 0; p < P; ++p) {
         if (!ok[p]) continue;
         if (a.n_split == 1) {
+            const int64_t oi = a.out_perm ? (int64_t)a.out_perm[idx[p]] : idx[p];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                const int64_t o = k * a.ld_out + idx[p];
+                const int64_t o = k * a.ld_out + oi;
                 a.out[o] = a.base ? a.base[o] - a.sign * acc[p][k] : (-a.sign) * acc[p][k];
             }
         } else {
@@ -244,11 +246,12 @@ __global__ __launch_bounds__(BLOCK) void ksum_finalize(KArgs a)
     for (int64_t w = (int64_t)blockIdx.x * BLOCK + threadIdx.x; w < n_work;
          w += (int64_t)gridDim.x * BLOCK) {
         const int64_t idx = a.work ? (int64_t)a.work[w] : w;
+        const int64_t oi = a.out_perm ? (int64_t)a.out_perm[idx] : idx;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             double s = 0.0;
             for (int sp = 0; sp < a.n_split; ++sp) s += a.partial[((int64_t)sp * DIM + k) * a.ld_part + w];
-            const int64_t o = k * a.ld_out + idx;
+            const int64_t o = k * a.ld_out + oi;
             a.out[o] = a.base ? a.base[o] - a.sign * s : (-a.sign) * s;
         }
     }
@@ -258,19 +261,37 @@ __global__ __launch_bounds__(BLOCK) void ksum_finalize(KArgs a)
 constexpr int CHUNK = 4;                  // points per lane in the compaction
 constexpr int CBLK = BLOCK * CHUNK;       // points per compaction block
 
-__global__ void zero_count(int64_t *n)
+__global__ __launch_bounds__(BLOCK) void reduce_count(const double *d, int64_t n, double dmax,
+                                                     int32_t *counts)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *n = 0;
+    __shared__ int32_t red[BLOCK];
+    const int64_t base = (int64_t)blockIdx.x * CBLK + (int64_t)threadIdx.x * CHUNK;
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < CHUNK; ++j)
+        if (base + j < n && d[base + j] < dmax) ++c;
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) counts[blockIdx.x] = red[0];
 }
 
-// Compaction of {v : d_v < dmax} in one pass: a block-local prefix sum of the kept points, then
-// one atomic reservation per block in the work list. Dropped points get +0.0 in every component.
-__global__ __launch_bounds__(BLOCK) void reduce_compact(const double *d, int64_t n, double dmax,
-                                                       int64_t *count, int32_t *work, double *out,
-                                                       int32_t dim)
+// Stable compaction of {v : d_v < dmax}: each block adds up the counts of the blocks before it
+// (a fixed-order sum, so the list is the same every run), scans its own flags and writes its
+// kept indices in order. Dropped points get +0.0 in every component; the last block stores
+// the total.
+__global__ __launch_bounds__(BLOCK) void reduce_scatter(const double *d, int64_t n, double dmax,
+                                                       const int32_t *counts, int64_t *n_work,
+                                                       int32_t *work, double *out, int32_t dim)
 {
     __shared__ int32_t sc[BLOCK];
-    __shared__ int64_t base_pos;
+    __shared__ int64_t red[BLOCK];
+    int64_t before = 0;
+    for (int64_t b = threadIdx.x; b < blockIdx.x; b += BLOCK) before += counts[b];
+    red[threadIdx.x] = before;
     const int64_t base = (int64_t)blockIdx.x * CBLK + (int64_t)threadIdx.x * CHUNK;
     bool keep[CHUNK];
     int c = 0;
@@ -281,17 +302,19 @@ __global__ __launch_bounds__(BLOCK) void reduce_compact(const double *d, int64_t
     }
     sc[threadIdx.x] = c;
     __syncthreads();
+    for (int s = BLOCK / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
     for (int s = 1; s < BLOCK; s <<= 1) {
         const int32_t t = threadIdx.x >= s ? sc[threadIdx.x - s] : 0;
         __syncthreads();
         sc[threadIdx.x] += t;
         __syncthreads();
     }
-    if (threadIdx.x == BLOCK - 1)
-        base_pos = (int64_t)atomicAdd(reinterpret_cast<unsigned long long *>(count),
-                                      (unsigned long long)sc[BLOCK - 1]);
-    __syncthreads();
-    int64_t pos = base_pos + sc[threadIdx.x] - c;
+    const int64_t block_off = red[0];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == BLOCK - 1) *n_work = block_off + sc[BLOCK - 1];
+    int64_t pos = block_off + sc[threadIdx.x] - c;
 #pragma unroll
     for (int j = 0; j < CHUNK; ++j) {
         const int64_t v = base + j;
@@ -304,24 +327,15 @@ __global__ __launch_bounds__(BLOCK) void reduce_compact(const double *d, int64_t
     }
 }
 
-// Sorted wall distances: the reduced volume is the prefix d < dmax (first index with d >= dmax).
-__global__ void reduce_prefix(const double *d, int64_t n, double dmax, int64_t *n_work)
+__global__ __launch_bounds__(BLOCK) void zero_tail(const int64_t *from, int64_t start_h, int64_t n,
+                                                  int32_t dim, const int32_t *perm, double *out)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        if (d[mid] < dmax) lo = mid + 1; else hi = mid;
-    }
-    *n_work = lo;
-}
-
-__global__ __launch_bounds__(BLOCK) void zero_tail(const int64_t *from, int64_t n, int32_t dim, double *out)
-{
-    const int64_t start = *from;
+    const int64_t start = from ? *from : start_h;
     for (int64_t v = start + (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * BLOCK)
-        for (int k = 0; k < dim; ++k) out[k * n + v] = 0.0;
+         v += (int64_t)gridDim.x * BLOCK) {
+        const int64_t o = perm ? (int64_t)perm[v] : v;
+        for (int k = 0; k < dim; ++k) out[k * n + o] = 0.0;
+    }
 }
 
 template <int DIM, int P>
@@ -374,21 +388,31 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     a.ld_out = pb.n_p;
     a.n_work = pb.n_p;
 
-    DevBuf work, nwork, partial;
-    if (pb.dwall) {
+    DevBuf work, nwork, partial, counts;
+    int64_t n_rows = pb.n_p;    // rows the kernel-sum grid covers
+    if (pb.dwall && pb.n_active >= 0) {
+        // Resident geometry: prefix of the wall-distance order, results through perm.
+        a.out_perm = pb.perm;
+        a.n_work = pb.n_active;
+        n_rows = pb.n_active;
+        if (pb.n_active < pb.n_p) {
+            const int gz = (int)std::min<int64_t>((pb.n_p - pb.n_active + BLOCK - 1) / BLOCK, 4096);
+            hipLaunchKernelGGL(zero_tail, dim3(gz), dim3(BLOCK), 0, s, (const int64_t *)nullptr,
+                               pb.n_active, pb.n_p, DIM, pb.perm, pb.out);
+            RBF_HIP(hipGetLastError());
+        }
+        if (pb.n_active == 0) return RBF_OK;
+    } else if (pb.dwall) {
         RBF_TRY(nwork.get(ctx->pool.get(), sizeof(int64_t)));
-        if (pb.sorted_by_d) {
-            hipLaunchKernelGGL(reduce_prefix, dim3(1), dim3(64), 0, s, pb.dwall, pb.n_p, dmax,
-                               nwork.as<int64_t>());
-            const int gz = (int)std::min<int64_t>((pb.n_p + BLOCK - 1) / BLOCK, 4096);
-            hipLaunchKernelGGL(zero_tail, dim3(gz), dim3(BLOCK), 0, s, nwork.as<int64_t>(), pb.n_p,
-                               DIM, pb.out);
-        } else {
+        {
             const int64_t nb = (pb.n_p + CBLK - 1) / CBLK;
             RBF_TRY(work.get(ctx->pool.get(), sizeof(int32_t) * pb.n_p));
-            hipLaunchKernelGGL(zero_count, dim3(1), dim3(64), 0, s, nwork.as<int64_t>());
-            hipLaunchKernelGGL(reduce_compact, dim3((unsigned)nb), dim3(BLOCK), 0, s, pb.dwall, pb.n_p,
-                               dmax, nwork.as<int64_t>(), work.as<int32_t>(), pb.out, DIM);
+            RBF_TRY(counts.get(ctx->pool.get(), sizeof(int32_t) * nb));
+            hipLaunchKernelGGL(reduce_count, dim3((unsigned)nb), dim3(BLOCK), 0, s, pb.dwall, pb.n_p,
+                               dmax, counts.as<int32_t>());
+            hipLaunchKernelGGL(reduce_scatter, dim3((unsigned)nb), dim3(BLOCK), 0, s, pb.dwall, pb.n_p,
+                               dmax, counts.as<const int32_t>(), nwork.as<int64_t>(), work.as<int32_t>(),
+                               pb.out, DIM);
             a.work = work.as<int32_t>();
         }
         RBF_HIP(hipGetLastError());
@@ -399,16 +423,16 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     const bool mixed = pb.precision == RBF_MIXED;
     int P = env_int("RBF_KSUM_P", 2);
     if (P != 1 && P != 2 && P != 4) P = 2;
-    const int64_t nbx = (pb.n_p + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
+    const int64_t nbx = (n_rows + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
     const int64_t target = (int64_t)env_int("RBF_KSUM_BLOCKS", 8 * ctx->n_cu);
     int S = (int)std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, nc_max / 32));
     S = std::min(S, env_int("RBF_KSUM_MAX_SPLIT", 64));
     if (const char *e = getenv("RBF_KSUM_SPLIT")) S = std::max(1, atoi(e));
     a.n_split = S;
     if (S > 1) {
-        RBF_TRY(partial.get(ctx->pool.get(), sizeof(double) * (size_t)S * DIM * pb.n_p));
+        RBF_TRY(partial.get(ctx->pool.get(), sizeof(double) * (size_t)S * DIM * n_rows));
         a.partial = partial.as<double>();
-        a.ld_part = pb.n_p;
+        a.ld_part = n_rows;
     }
     const dim3 grid((unsigned)nbx, (unsigned)S);
     hipEvent_t t0;
@@ -419,12 +443,13 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     ctx->timers.end(pb.dwall ? (mixed ? "volume_ksum_mixed" : "volume_ksum_fp64")
                              : (mixed ? "surface_ksum_mixed" : "surface_ksum_fp64"), t0, s);
     if (S > 1) {
-        const int gf = (int)std::min<int64_t>((pb.n_p + BLOCK - 1) / BLOCK, 8192);
+        const int gf = (int)std::min<int64_t>((n_rows + BLOCK - 1) / BLOCK, 8192);
         if (DIM == 2) hipLaunchKernelGGL(ksum_finalize<2>, dim3(gf), dim3(BLOCK), 0, s, a);
         else hipLaunchKernelGGL(ksum_finalize<3>, dim3(gf), dim3(BLOCK), 0, s, a);
         RBF_HIP(hipGetLastError());
     }
     work.release_after(s);
+    counts.release_after(s);
     nwork.release_after(s);
     partial.release_after(s);
     return RBF_OK;

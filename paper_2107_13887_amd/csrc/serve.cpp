@@ -1,35 +1,569 @@
-// Serving loop: resident geometries and asynchronous deformation requests.
+// Serving: resident geometries and asynchronous deformation requests with continuous batching.
+//
+// Geometry. rbf_geom_create copies the surface and volume into the context's pool, computes the
+// wall distance when none is given (distance to the nearest surface point), and stores the volume
+// in wall-distance order: a stable counting sort over bins taken from the FP64 bit pattern of d
+// (exactly monotone in d, roughly logarithmic). The reduced volume of any request, {d < max D_l},
+// is then a prefix whose end the host knows from the bin offsets (section 4's volume point
+// reduction without any per-request compaction); results go back through the permutation.
+//
+// Requests. rbf_submit copies the request and queues it. Worker slots, each with its own HIP
+// stream, pull requests in arrival order as soon as they are free: a request is admitted when its
+// device-memory footprint fits the part of the HBM budget that running requests have not
+// reserved, and when no earlier request on the same geometry is still pending (successive icing
+// steps run in order, each warm-started from the control sets its predecessor selected). Work of
+// different requests overlaps on the device. Each request's kernels and launch shapes depend only
+// on its own sizes, so its results are the same alone and in a mix.
+#include <algorithm>
+#include <cmath>
+
 #include "internal.h"
 
 namespace rbf {
-class Server {};
+namespace {
+
+constexpr int NBIN = 1024;
+constexpr int SORT_BLK = 2048;
+
+__device__ __host__ inline uint64_t dbits(double d)
+{
+    uint64_t u;
+    memcpy(&u, &d, sizeof u);
+    return u;
+}
+
+// Bin of a non-negative distance: (bits(d) - bits(lo)) >> shift, clamped. Monotone in d.
+__device__ __host__ inline int dist_bin(double d, uint64_t lo_bits, int shift)
+{
+    const uint64_t b = dbits(d);
+    if (b <= lo_bits) return 0;
+    const uint64_t k = (b - lo_bits) >> shift;
+    return k >= (uint64_t)NBIN ? NBIN - 1 : (int)k;
+}
+
+// d_v = min_s ||x_v - x_s|| over the surface points (surface staged through LDS).
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_walldist(const double *xs, int64_t n_s, const double *xv,
+                                                    int64_t n_v, double *d)
+{
+    __shared__ double tile[256 * DIM];
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double x[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) x[k] = v < n_v ? xv[k * n_v + v] : 0.0;
+    double best = 1e300;
+    for (int64_t t0 = 0; t0 < n_s; t0 += 256) {
+        const int nt = (int)min<int64_t>(256, n_s - t0);
+        __syncthreads();
+        if (threadIdx.x < nt)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) tile[threadIdx.x * DIM + k] = xs[k * n_s + t0 + threadIdx.x];
+        __syncthreads();
+        for (int j = 0; j < nt; ++j) {
+            double r2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const double dk = x[k] - tile[j * DIM + k];
+                r2 = __builtin_fma(dk, dk, r2);
+            }
+            best = fmin(best, r2);
+        }
+    }
+    if (v < n_v) d[v] = sqrt(best);
+}
+
+__global__ __launch_bounds__(256) void geo_minmax(const double *d, int64_t n, unsigned long long *mm)
+{
+    // mm[0] = bits of the smallest positive distance, mm[1] = bits of the largest (exact).
+    unsigned long long lo = ~0ull, hi = 0ull;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const unsigned long long b = dbits(d[i]);
+        if (d[i] > 0.0 && b < lo) lo = b;
+        if (b > hi) hi = b;
+    }
+    atomicMin(&mm[0], lo);
+    atomicMax(&mm[1], hi);
+}
+
+// Per-block bin histograms, stored bin-major: hist[bin * nblk + block].
+__global__ __launch_bounds__(256) void geo_hist(const double *d, int64_t n, uint64_t lo_bits, int shift,
+                                                int32_t *hist, int64_t nblk)
+{
+    __shared__ int32_t h[NBIN];
+    for (int b = threadIdx.x; b < NBIN; b += 256) h[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * SORT_BLK;
+    for (int j = threadIdx.x; j < SORT_BLK; j += 256)
+        if (base + j < n) atomicAdd(&h[dist_bin(d[base + j], lo_bits, shift)], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < NBIN; b += 256) hist[(int64_t)b * nblk + blockIdx.x] = h[b];
+}
+
+// Exclusive scan of the bin-major histogram table by one workgroup (fixed order).
+__global__ __launch_bounds__(1024) void geo_scan(int32_t *hist, int64_t m)
+{
+    __shared__ int64_t part[1024];
+    const int64_t per = (m + 1023) / 1024;
+    const int64_t b0 = threadIdx.x * per, b1 = min<int64_t>(m, b0 + per);
+    int64_t s = 0;
+    for (int64_t i = b0; i < b1; ++i) s += hist[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int64_t i = b0; i < b1; ++i) {
+        const int32_t v = hist[i];
+        hist[i] = (int32_t)run;
+        run += v;
+    }
+}
+
+// Stable placement: positions assigned in index order inside each block (one lane walks the
+// block), then the copies run on all lanes. perm[pos] = original index.
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_place(const double *d, const double *xv, int64_t n,
+                                                 uint64_t lo_bits, int shift, const int32_t *off,
+                                                 int64_t nblk, int32_t *perm, double *d_sorted,
+                                                 double *xv_sorted)
+{
+    __shared__ int32_t cur[NBIN];
+    __shared__ int32_t pos[SORT_BLK];
+    const int64_t base = (int64_t)blockIdx.x * SORT_BLK;
+    const int cnt = (int)min<int64_t>(SORT_BLK, n - base);
+    for (int b = threadIdx.x; b < NBIN; b += 256) cur[b] = off[(int64_t)b * nblk + blockIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int j = 0; j < cnt; ++j) pos[j] = cur[dist_bin(d[base + j], lo_bits, shift)]++;
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += 256) {
+        const int64_t v = base + j, p = pos[j];
+        perm[p] = (int32_t)v;
+        d_sorted[p] = d[v];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xv_sorted[k * n + p] = xv[k * n + v];
+    }
+}
+
+template <int DIM>
+rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const double *xv,
+                          const double *dwall, hipStream_t s)
+{
+    Pool *pool = ctx->pool.get();
+    const int64_t n_s = g.n_s, n_v = g.n_v;
+    RBF_TRY(g.xs.get(pool, sizeof(double) * DIM * n_s));
+    RBF_HIP(hipMemcpyAsync(g.xs.ptr, xs, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
+    RBF_TRY(g.xv_sorted.get(pool, sizeof(double) * DIM * std::max<int64_t>(1, n_v)));
+    RBF_TRY(g.d_sorted.get(pool, sizeof(double) * std::max<int64_t>(1, n_v)));
+    RBF_TRY(g.perm.get(pool, sizeof(int32_t) * std::max<int64_t>(1, n_v)));
+    g.bytes = sizeof(double) * (DIM * (n_s + n_v) + n_v) + sizeof(int32_t) * n_v;
+    g.bin_off.assign(NBIN + 1, (int32_t)n_v);
+    g.bin_off[0] = 0;
+    g.lo_bits = 0;
+    g.shift = 0;
+    if (n_v == 0) return RBF_OK;
+    DevBuf dtmp, mm, hist;
+    const double *d = dwall;
+    if (!d) {
+        RBF_TRY(dtmp.get(pool, sizeof(double) * n_v));
+        hipLaunchKernelGGL(geo_walldist<DIM>, dim3((unsigned)((n_v + 255) / 256)), dim3(256), 0, s,
+                           g.xs.as<double>(), n_s, xv, n_v, dtmp.as<double>());
+        RBF_HIP(hipGetLastError());
+        d = dtmp.as<double>();
+    }
+    RBF_TRY(mm.get(pool, 2 * sizeof(unsigned long long)));
+    unsigned long long init[2] = {~0ull, 0ull};
+    RBF_HIP(hipMemcpyAsync(mm.ptr, init, sizeof init, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(geo_minmax, dim3((unsigned)std::min<int64_t>((n_v + 255) / 256, 1024)), dim3(256), 0, s,
+                       d, n_v, mm.as<unsigned long long>());
+    unsigned long long mmh[2];
+    RBF_HIP(hipMemcpyAsync(mmh, mm.ptr, sizeof mmh, hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    uint64_t lo = mmh[0] == ~0ull ? mmh[1] : mmh[0];
+    const uint64_t span = mmh[1] > lo ? mmh[1] - lo : 0;
+    int shift = 0;
+    while ((span >> shift) >= (uint64_t)NBIN) ++shift;
+    g.lo_bits = lo;
+    g.shift = shift;
+    const int64_t nblk = (n_v + SORT_BLK - 1) / SORT_BLK;
+    RBF_TRY(hist.get(pool, sizeof(int32_t) * NBIN * nblk));
+    hipLaunchKernelGGL(geo_hist, dim3((unsigned)nblk), dim3(256), 0, s, d, n_v, lo, shift, hist.as<int32_t>(), nblk);
+    hipLaunchKernelGGL(geo_scan, dim3(1), dim3(1024), 0, s, hist.as<int32_t>(), (int64_t)NBIN * nblk);
+    hipLaunchKernelGGL(geo_place<DIM>, dim3((unsigned)nblk), dim3(256), 0, s, d, xv, n_v, lo, shift,
+                       hist.as<const int32_t>(), nblk, g.perm.as<int32_t>(), g.d_sorted.as<double>(),
+                       g.xv_sorted.as<double>());
+    RBF_HIP(hipGetLastError());
+    // Bin starts (offset of block 0 of each bin) for the host-side prefix lookups.
+    std::vector<int32_t> starts(NBIN);
+    RBF_HIP(hipMemcpy2DAsync(starts.data(), sizeof(int32_t), hist.ptr, sizeof(int32_t) * nblk,
+                             sizeof(int32_t), NBIN, hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < NBIN; ++b) g.bin_off[b] = starts[b];
+    g.bin_off[NBIN] = (int32_t)n_v;
+    return RBF_OK;
+}
+
+// Reduced-volume prefix for support distance D: every point of every bin up to bin(D).
+int64_t prefix_for(const Geometry &g, double D)
+{
+    if (g.n_v == 0) return 0;
+    const int b = dist_bin(D, g.lo_bits, g.shift);
+    return g.bin_off[std::min(NBIN, b + 1)];
+}
+
+uint64_t greedy_footprint(int dim, int64_t n_s, int64_t cap)
+{
+    const uint64_t cols = (uint64_t)std::min<int64_t>(n_s, cap);
+    return sizeof(double) * (cols * (uint64_t)n_s + cols * (cols + 1) / 2 + (uint64_t)(3 * dim + 1) * n_s +
+                             (uint64_t)(dim + 1) * cols + 2 * (uint64_t)cap) +
+           (uint64_t)n_s * 17 + sizeof(int64_t) * (uint64_t)cap + sizeof(double) * (uint64_t)cap * 2 * dim;
+}
+
+}  // namespace
+
+// ---- server ---------------------------------------------------------------------------------
+struct Req {
+    rbf_ticket id = 0;
+    rbf_request r{};
+    std::vector<int64_t> seed_idx;
+    std::vector<int32_t> seed_off;
+    Geometry *g = nullptr;
+    rbf_geom handle = nullptr;
+    int32_t state = RBF_REQ_QUEUED;
+    rbf_status result = RBF_OK;
+    double t_arrive = 0, t_admit = 0, t_start = 0, t_done = 0;
+    uint64_t reserve = 0;
+};
+
+class Server {
+  public:
+    explicit Server(rbf_ctx ctx, int n_slots) : ctx_(ctx)
+    {
+        for (int i = 0; i < n_slots; ++i) {
+            hipStream_t s = nullptr;
+            (void)hipSetDevice(ctx->device);
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) break;
+            streams_.push_back(s);
+        }
+        for (size_t i = 0; i < streams_.size(); ++i) workers_.emplace_back([this, i] { work(i); });
+    }
+    ~Server()
+    {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+            for (Req *q : queue_) {
+                q->state = RBF_REQ_FAILED;
+                q->result = fail(RBF_E_DEVICE, "context destroyed before the request ran");
+            }
+            queue_.clear();
+        }
+        cv_.notify_all();
+        for (auto &t : workers_) t.join();
+        for (auto s : streams_) (void)hipStreamDestroy(s);
+    }
+    bool ok() const { return !streams_.empty(); }
+
+    rbf_status submit(std::unique_ptr<Req> q, rbf_ticket *out)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        q->id = ++next_id_;
+        q->t_arrive = now_seconds();
+        q->g->refs += 1;
+        *out = q->id;
+        queue_.push_back(q.get());
+        reqs_[q->id] = std::move(q);
+        cv_.notify_all();
+        return RBF_OK;
+    }
+
+    rbf_status poll(rbf_ticket t, rbf_req_info *info, bool wait)
+    {
+        std::unique_lock<std::mutex> lk(mu_);
+        auto it = reqs_.find(t);
+        if (it == reqs_.end()) return fail(RBF_E_NOT_FOUND, "unknown ticket %llu", (unsigned long long)t);
+        Req *q = it->second.get();
+        if (wait)
+            done_cv_.wait(lk, [&] { return q->state == RBF_REQ_DONE || q->state == RBF_REQ_FAILED; });
+        info->state = q->state;
+        info->result = q->result;
+        info->t_arrive = q->t_arrive;
+        info->t_admit = q->t_admit;
+        info->t_start = q->t_start;
+        info->t_done = q->t_done;
+        if (wait) reqs_.erase(it);
+        return RBF_OK;
+    }
+
+    bool geometry_busy(Geometry *g)
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        return g->refs > 0;
+    }
+
+  private:
+    // First admissible request in arrival order: its geometry has no earlier pending request and
+    // its footprint fits the unreserved budget. An earlier request that does not fit the memory
+    // blocks the later ones (no starvation of large requests).
+    Req *pick_locked()
+    {
+        const uint64_t budget = ctx_->pool->budget();
+        std::vector<Geometry *> blocked;
+        for (auto it = queue_.begin(); it != queue_.end(); ++it) {
+            Req *q = *it;
+            if (std::find(blocked.begin(), blocked.end(), q->g) != blocked.end() || q->g->running) {
+                blocked.push_back(q->g);
+                continue;
+            }
+            if (reserved_ + q->reserve > budget) return nullptr;
+            queue_.erase(it);
+            return q;
+        }
+        return nullptr;
+    }
+
+    void work(size_t slot)
+    {
+        (void)hipSetDevice(ctx_->device);
+        hipStream_t s = streams_[slot];
+        for (;;) {
+            Req *q = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || (q = pick_locked()) != nullptr; });
+                if (!q) return;   // stopping
+                reserved_ += q->reserve;
+                q->g->running = true;
+                q->state = RBF_REQ_RUNNING;
+                q->t_admit = now_seconds();
+            }
+            q->t_start = now_seconds();
+            const rbf_status st = run(*q, s);
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                q->t_done = now_seconds();
+                q->result = st;
+                q->state = st < 0 ? RBF_REQ_FAILED : RBF_REQ_DONE;
+                reserved_ -= q->reserve;
+                q->g->running = false;
+                q->g->refs -= 1;
+            }
+            cv_.notify_all();
+            done_cv_.notify_all();
+        }
+    }
+
+    rbf_status run(Req &q, hipStream_t s);
+
+    rbf_ctx ctx_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    std::deque<Req *> queue_;
+    std::unordered_map<rbf_ticket, std::unique_ptr<Req>> reqs_;
+    std::vector<hipStream_t> streams_;
+    std::vector<std::thread> workers_;
+    uint64_t reserved_ = 0;
+    rbf_ticket next_id_ = 0;
+    bool stop_ = false;
+};
+
+rbf_status Server::run(Req &q, hipStream_t s)
+{
+    Geometry &g = *q.g;
+    const rbf_greedy_params &p0 = q.r.params;
+    rbf_greedy_params p = p0;
+    // Warm start: seed every level with the control set the previous request on this geometry
+    // selected (if it fits the cap); otherwise the request's own seeds.
+    std::vector<int64_t> wseed;
+    std::vector<int32_t> woff;
+    if (q.r.warm_start && (int)g.last_ctrl.size() == p.n_levels) {
+        woff.assign(p.n_levels + 1, 0);
+        for (int l = 0; l < p.n_levels; ++l) {
+            for (int64_t c : g.last_ctrl[l]) wseed.push_back(c);
+            woff[l + 1] = (int32_t)wseed.size();
+        }
+        if ((int64_t)wseed.size() <= p.max_ctrl_total && !wseed.empty()) {
+            p.seed_idx = wseed.data();
+            p.seed_off = woff.data();
+        }
+    } else if (!q.seed_off.empty()) {
+        p.seed_idx = q.seed_idx.data();
+        p.seed_off = q.seed_off.data();
+    } else {
+        p.seed_idx = nullptr;
+        p.seed_off = nullptr;
+    }
+    const int dim = p.dim;
+    const int64_t cap = p.max_ctrl_total;
+    rbf_ctrl_set local{};
+    rbf_ctrl_set *cs = q.r.out;
+    DevBuf bi, bx, ba;
+    if (!cs) {
+        RBF_TRY(bi.get(ctx_->pool.get(), sizeof(int64_t) * cap));
+        RBF_TRY(bx.get(ctx_->pool.get(), sizeof(double) * dim * cap));
+        RBF_TRY(ba.get(ctx_->pool.get(), sizeof(double) * dim * cap));
+        local.capacity = cap;
+        local.ctrl_idx = bi.as<int64_t>();
+        local.xc = bx.as<double>();
+        local.alpha = ba.as<double>();
+        local.e_final = nullptr;
+        cs = &local;
+    }
+    rbf_status st = run_greedy(ctx_, p, g.n_s, g.xs.as<double>(), q.r.ds, cs, s);
+    if (st < 0) return st;
+    // Volume update on the resident, wall-distance-ordered volume.
+    SumProblem pb;
+    pb.dim = dim;
+    pb.n_levels = p.n_levels;
+    double dmax = 0.0;
+    for (int l = 0; l < p.n_levels; ++l) {
+        pb.lv[l] = SumLevel{1.0 / p.radius[l], q.r.D[l], cs->level_off[l], cs->level_off[l + 1]};
+        dmax = std::max(dmax, q.r.D[l]);
+    }
+    pb.ld_ctrl = cs->capacity;
+    pb.xc = cs->xc;
+    pb.alpha = cs->alpha;
+    pb.n_p = g.n_v;
+    pb.xp = g.xv_sorted.as<double>();
+    pb.dwall = g.d_sorted.as<double>();
+    pb.perm = g.perm.as<int32_t>();
+    pb.n_active = prefix_for(g, dmax);
+    pb.out = q.r.dv;
+    pb.sign = -1.0;
+    pb.precision = p.precision;
+    RBF_TRY(run_kernel_sum(ctx_, pb, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    // Remember the control sets for the next icing step on this geometry.
+    std::vector<int64_t> all(cs->level_off[p.n_levels]);
+    if (!all.empty())
+        RBF_HIP(hipMemcpy(all.data(), cs->ctrl_idx, sizeof(int64_t) * all.size(), hipMemcpyDeviceToHost));
+    g.last_ctrl.assign(p.n_levels, {});
+    for (int l = 0; l < p.n_levels; ++l)
+        g.last_ctrl[l].assign(all.begin() + cs->level_off[l], all.begin() + cs->level_off[l + 1]);
+    return st;
+}
 
 void server_shutdown(rbf_ctx ctx)
 {
     delete ctx->server;
     ctx->server = nullptr;
 }
+
 }  // namespace rbf
 
 using namespace rbf;
 
 extern "C" {
 
-rbf_status rbf_geom_create(rbf_ctx, int32_t, int64_t, const double *, int64_t, const double *,
-                           const double *, rbf_geom *)
+rbf_status rbf_geom_create(rbf_ctx ctx, int32_t dim, int64_t n_s, const double *xs, int64_t n_v,
+                           const double *xv, const double *dwall, rbf_geom *out)
 {
-    return fail(RBF_E_INVALID, "serving not available in this build");
+    if (!ctx || !out) return fail(RBF_E_INVALID, "NULL context or out");
+    if (dim != 2 && dim != 3) return fail(RBF_E_INVALID, "dim must be 2 or 3");
+    if (n_s < 1 || n_s > (int64_t(1) << 31) - 1) return fail(RBF_E_INVALID, "n_s out of range");
+    if (n_v < 0 || n_v > (int64_t(1) << 31) - 1) return fail(RBF_E_INVALID, "n_v out of range");
+    if (!xs || (n_v > 0 && !xv)) return fail(RBF_E_INVALID, "NULL device array");
+    RBF_HIP(hipSetDevice(ctx->device));
+    auto g = std::make_unique<Geometry>();
+    g->dim = dim;
+    g->n_s = n_s;
+    g->n_v = n_v;
+    hipStream_t s = nullptr;
+    RBF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    rbf_status st = dim == 2 ? build_geometry<2>(ctx, *g, xs, xv, dwall, s)
+                             : build_geometry<3>(ctx, *g, xs, xv, dwall, s);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    if (st < 0) return st;
+    rbf_geom h = reinterpret_cast<rbf_geom>(g.get());
+    std::lock_guard<std::mutex> lk(ctx->geom_mu);
+    ctx->geoms[h] = std::move(g);
+    *out = h;
+    return RBF_OK;
 }
 
-rbf_status rbf_geom_release(rbf_ctx, rbf_geom) { return fail(RBF_E_NOT_FOUND, "no geometry"); }
-
-rbf_status rbf_submit(rbf_ctx, const rbf_request *, rbf_ticket *)
+rbf_status rbf_geom_release(rbf_ctx ctx, rbf_geom geom)
 {
-    return fail(RBF_E_INVALID, "serving not available in this build");
+    if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(ctx->geom_mu);
+    auto it = ctx->geoms.find(geom);
+    if (it == ctx->geoms.end()) return fail(RBF_E_NOT_FOUND, "unknown geometry");
+    if (ctx->server && ctx->server->geometry_busy(it->second.get()))
+        return fail(RBF_E_BUSY, "geometry still has queued or running requests");
+    ctx->geoms.erase(it);
+    return RBF_OK;
 }
 
-rbf_status rbf_poll(rbf_ctx, rbf_ticket, rbf_req_info *) { return fail(RBF_E_NOT_FOUND, "no ticket"); }
+rbf_status rbf_submit(rbf_ctx ctx, const rbf_request *req, rbf_ticket *out)
+{
+    if (!ctx || !req || !out) return fail(RBF_E_INVALID, "NULL argument");
+    Geometry *g = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->geom_mu);
+        auto it = ctx->geoms.find(req->geom);
+        if (it == ctx->geoms.end()) return fail(RBF_E_NOT_FOUND, "unknown geometry");
+        g = it->second.get();
+    }
+    const rbf_greedy_params &p = req->params;
+    RBF_TRY(validate_params(p, g->n_s));
+    if (p.dim != g->dim) return fail(RBF_E_INVALID, "request dim %d != geometry dim %d", p.dim, g->dim);
+    if (!req->ds || (g->n_v > 0 && !req->dv)) return fail(RBF_E_INVALID, "NULL device array");
+    for (int l = 0; l < p.n_levels; ++l)
+        if (!(req->D[l] > 0.0) || !std::isfinite(req->D[l])) return fail(RBF_E_INVALID, "D[%d] must be > 0", l);
+    if (req->out && (!req->out->ctrl_idx || !req->out->xc || !req->out->alpha ||
+                     req->out->capacity < p.max_ctrl_total))
+        return fail(RBF_E_INVALID, "out control set arrays missing or too small");
+    auto q = std::make_unique<Req>();
+    q->r = *req;
+    q->g = g;
+    q->handle = req->geom;
+    if (p.seed_off) {
+        q->seed_off.assign(p.seed_off, p.seed_off + p.n_levels + 1);
+        q->seed_idx.assign(p.seed_idx, p.seed_idx + p.seed_off[p.n_levels]);
+    }
+    q->r.params.seed_idx = nullptr;
+    q->r.params.seed_off = nullptr;
+    const int64_t n_act = g->n_v;
+    q->reserve = greedy_footprint(p.dim, g->n_s, p.max_ctrl_total) +
+                 sizeof(double) * (uint64_t)p.dim * (uint64_t)n_act * 2 + (64ull << 20);
+    if (q->reserve > ctx->pool->budget())
+        return fail(RBF_E_NOMEM, "request needs about %llu bytes, budget is %llu",
+                    (unsigned long long)q->reserve, (unsigned long long)ctx->pool->budget());
+    {
+        std::lock_guard<std::mutex> lk(ctx->geom_mu);
+        if (!ctx->server) {
+            const char *e = getenv("RBF_SERVE_SLOTS");
+            const int slots = e && atoi(e) > 0 ? atoi(e) : 4;
+            ctx->server = new Server(ctx, slots);
+            if (!ctx->server->ok()) {
+                delete ctx->server;
+                ctx->server = nullptr;
+                return fail(RBF_E_DEVICE, "could not create serving streams");
+            }
+        }
+    }
+    return ctx->server->submit(std::move(q), out);
+}
 
-rbf_status rbf_wait(rbf_ctx, rbf_ticket, rbf_req_info *) { return fail(RBF_E_NOT_FOUND, "no ticket"); }
+rbf_status rbf_poll(rbf_ctx ctx, rbf_ticket t, rbf_req_info *out)
+{
+    if (!ctx || !out) return fail(RBF_E_INVALID, "NULL argument");
+    if (!ctx->server) return fail(RBF_E_NOT_FOUND, "unknown ticket");
+    return ctx->server->poll(t, out, false);
+}
+
+rbf_status rbf_wait(rbf_ctx ctx, rbf_ticket t, rbf_req_info *out)
+{
+    if (!ctx || !out) return fail(RBF_E_INVALID, "NULL argument");
+    if (!ctx->server) return fail(RBF_E_NOT_FOUND, "unknown ticket");
+    return ctx->server->poll(t, out, true);
+}
 
 }  // extern "C"
