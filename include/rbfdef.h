@@ -196,6 +196,15 @@ typedef struct {
     double t_done;
 } rbf_req_info;
 
+/* Volume update of eqs. (19) and (23) on a resident geometry: the volume is stored in
+ * wall-distance order, so the reduced volume {d < max_l D_l} of section 4 is a prefix found from
+ * the stored bin offsets (no per-call compaction). Arguments as rbf_volume_update; dv is
+ * device [dim][n_v] in the geometry's original point order, fully written. Enqueued on stream. */
+rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, const double *radius,
+                                  const double *D, const int32_t *level_off, int64_t ld_ctrl,
+                                  const double *xc, const double *alpha, double *dv,
+                                  int32_t precision, void *stream);
+
 /* Non-blocking. RBF_E_NOMEM if the request could never fit the budget. */
 rbf_status rbf_submit(rbf_ctx ctx, const rbf_request *req, rbf_ticket *out);
 /* Non-blocking status query. A DONE/FAILED ticket stays queryable until rbf_wait returns it. */

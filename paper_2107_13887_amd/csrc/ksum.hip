@@ -327,17 +327,6 @@ __global__ __launch_bounds__(BLOCK) void reduce_scatter(const double *d, int64_t
     }
 }
 
-__global__ __launch_bounds__(BLOCK) void zero_tail(const int64_t *from, int64_t start_h, int64_t n,
-                                                  int32_t dim, const int32_t *perm, double *out)
-{
-    const int64_t start = from ? *from : start_h;
-    for (int64_t v = start + (int64_t)blockIdx.x * BLOCK + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * BLOCK) {
-        const int64_t o = perm ? (int64_t)perm[v] : v;
-        for (int k = 0; k < dim; ++k) out[k * n + o] = 0.0;
-    }
-}
-
 template <int DIM, int P>
 void launch_sum(const KArgs &a, dim3 grid, bool mixed, hipStream_t s)
 {
@@ -391,17 +380,10 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     DevBuf work, nwork, partial, counts;
     int64_t n_rows = pb.n_p;    // rows the kernel-sum grid covers
     if (pb.dwall && pb.n_active >= 0) {
-        // Resident geometry: prefix of the wall-distance order, results through perm.
+        // Resident geometry in wall-distance order: results go out through perm. The grid covers
+        // every point; blocks past the reduced prefix find no point with psi > 0, skip every
+        // level and write +0.0, so no separate zero-fill is launched.
         a.out_perm = pb.perm;
-        a.n_work = pb.n_active;
-        n_rows = pb.n_active;
-        if (pb.n_active < pb.n_p) {
-            const int gz = (int)std::min<int64_t>((pb.n_p - pb.n_active + BLOCK - 1) / BLOCK, 4096);
-            hipLaunchKernelGGL(zero_tail, dim3(gz), dim3(BLOCK), 0, s, (const int64_t *)nullptr,
-                               pb.n_active, pb.n_p, DIM, pb.perm, pb.out);
-            RBF_HIP(hipGetLastError());
-        }
-        if (pb.n_active == 0) return RBF_OK;
     } else if (pb.dwall) {
         RBF_TRY(nwork.get(ctx->pool.get(), sizeof(int64_t)));
         {
@@ -425,7 +407,9 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     if (P != 1 && P != 2 && P != 4) P = 2;
     const int64_t nbx = (n_rows + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
     const int64_t target = (int64_t)env_int("RBF_KSUM_BLOCKS", 8 * ctx->n_cu);
-    int S = (int)std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, nc_max / 32));
+    // Split only while every split keeps at least 128 controls: a split re-reads the points and
+    // writes partial sums, which pays only when it turns a ragged last round of waves into many.
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, nc_max / 128));
     S = std::min(S, env_int("RBF_KSUM_MAX_SPLIT", 64));
     if (const char *e = getenv("RBF_KSUM_SPLIT")) S = std::max(1, atoi(e));
     a.n_split = S;

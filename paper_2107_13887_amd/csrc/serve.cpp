@@ -489,6 +489,52 @@ rbf_status rbf_geom_create(rbf_ctx ctx, int32_t dim, int64_t n_s, const double *
     return RBF_OK;
 }
 
+rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, const double *radius,
+                                  const double *D, const int32_t *level_off, int64_t ld_ctrl,
+                                  const double *xc, const double *alpha, double *dv,
+                                  int32_t precision, void *stream)
+{
+    if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
+    Geometry *g = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(ctx->geom_mu);
+        auto it = ctx->geoms.find(geom);
+        if (it == ctx->geoms.end()) return fail(RBF_E_NOT_FOUND, "unknown geometry");
+        g = it->second.get();
+    }
+    if (n_levels < 1 || n_levels > RBF_MAX_LEVELS) return fail(RBF_E_INVALID, "n_levels out of range");
+    if (!radius || !D || !level_off) return fail(RBF_E_INVALID, "NULL host array");
+    if (level_off[0] < 0) return fail(RBF_E_INVALID, "level_off[0] < 0");
+    double dmax = 0.0;
+    for (int l = 0; l < n_levels; ++l) {
+        if (!(radius[l] > 0.0) || !std::isfinite(radius[l])) return fail(RBF_E_INVALID, "radius[%d] invalid", l);
+        if (!(D[l] > 0.0) || !std::isfinite(D[l])) return fail(RBF_E_INVALID, "D[%d] invalid", l);
+        if (level_off[l + 1] < level_off[l]) return fail(RBF_E_INVALID, "level_off not monotone");
+        dmax = std::max(dmax, D[l]);
+    }
+    if (level_off[n_levels] > ld_ctrl) return fail(RBF_E_INVALID, "level_off exceeds ld_ctrl");
+    if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_E_INVALID, "bad precision");
+    if (g->n_v == 0) return RBF_OK;
+    if (!dv || (level_off[n_levels] > level_off[0] && (!xc || !alpha))) return fail(RBF_E_INVALID, "NULL device array");
+    RBF_HIP(hipSetDevice(ctx->device));
+    SumProblem pb;
+    pb.dim = g->dim;
+    pb.n_levels = n_levels;
+    for (int l = 0; l < n_levels; ++l) pb.lv[l] = SumLevel{1.0 / radius[l], D[l], level_off[l], level_off[l + 1]};
+    pb.ld_ctrl = ld_ctrl;
+    pb.xc = xc;
+    pb.alpha = alpha;
+    pb.n_p = g->n_v;
+    pb.xp = g->xv_sorted.as<double>();
+    pb.dwall = g->d_sorted.as<double>();
+    pb.perm = g->perm.as<int32_t>();
+    pb.n_active = prefix_for(*g, dmax);
+    pb.out = dv;
+    pb.sign = -1.0;
+    pb.precision = precision;
+    return run_kernel_sum(ctx, pb, (hipStream_t)stream);
+}
+
 rbf_status rbf_geom_release(rbf_ctx ctx, rbf_geom geom)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");

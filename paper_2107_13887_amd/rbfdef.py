@@ -68,6 +68,8 @@ _SIGS = {
     "rbf_evaluate": (_i32, [_vp, _i32, _f64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _f64, _vp, _i32, _vp]),
     "rbf_geom_create": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_vp)]),
     "rbf_geom_release": (_i32, [_vp, _vp]),
+    "rbf_geom_volume_update": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
+                                      ctypes.POINTER(_i32), _i64, _vp, _vp, _vp, _i32, _vp]),
     "rbf_submit": (_i32, [_vp, ctypes.POINTER(rbf_request), ctypes.POINTER(_u64)]),
     "rbf_poll": (_i32, [_vp, _u64, ctypes.POINTER(rbf_req_info)]),
     "rbf_wait": (_i32, [_vp, _u64, ctypes.POINTER(rbf_req_info)]),
@@ -344,6 +346,31 @@ def rbf_geom_create(ctx: int, xs, xv, dwall=None) -> int:
     h = _vp()
     _check(lib().rbf_geom_create(ctx, dim, n_s, pxs, n_v, pxv, pd, ctypes.byref(h)), "rbf_geom_create")
     return h.value
+
+
+def rbf_geom_volume_update(ctx: int, geom: int, radius: Sequence[float], D: Sequence[float],
+                           level_off: Sequence[int], xc, alpha, dv, precision: str = "fp64", stream=None):
+    """Enqueue the volume update on a resident geometry (prefix of its wall-distance order);
+    dv is [dim, n_v] in the geometry's original point order."""
+    nl = len(radius)
+    if len(level_off) != nl + 1:
+        raise ValueError("level_off must have n_levels + 1 entries")
+    D = list(D) if len(D) == nl else [float(D[0])] * nl
+    dim = dv.shape[0]
+    pxc, ldc = _dev(xc, "xc", dim, None, allow_ld=True)
+    pa, lda = _dev(alpha, "alpha", dim, None, allow_ld=True)
+    if ldc != lda:
+        raise ValueError("xc and alpha must share a leading dimension")
+    if int(level_off[-1]) > xc.shape[1]:
+        raise ValueError("level_off exceeds the control arrays")
+    pdv, _ = _dev(dv, "dv", dim, None)
+    r = (_f64 * nl)(*[float(x) for x in radius])
+    d = (_f64 * nl)(*[float(x) for x in D])
+    off = (_i32 * (nl + 1))(*[int(x) for x in level_off])
+    _check(lib().rbf_geom_volume_update(ctx, geom, nl, r, d, off, ldc, pxc, pa, pdv,
+                                        RBF_MIXED if precision == "mixed" else RBF_FP64, _stream(stream)),
+           "rbf_geom_volume_update")
+    return dv
 
 
 def rbf_geom_release(ctx: int, geom: int) -> int:

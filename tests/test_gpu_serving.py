@@ -169,3 +169,26 @@ def test_bad_handles(gctx):
     with pytest.raises(rbfdef.RbfError) as e:
         rbfdef.rbf_geom_release(gctx, 12345)
     assert e.value.status == rbfdef.RBF_E_NOT_FOUND
+
+
+def test_geom_volume_update_matches_oracle(gctx, orc):
+    """The resident-geometry volume update equals the oracle's volume update for given control
+    sets (per-level D, ragged sizes, 3D)."""
+    w = synth.random_workload(77, 3, 500, 9001, [1.5, 0.6], 1e-7)
+    ref = orc.greedy(3, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds)
+    xc = np.ascontiguousarray(w.xs[:, ref.ctrl_idx])
+    D = [0.9, 0.45]
+    geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
+    dv = torch.full((3, w.n_v), float("nan"), dtype=torch.float64, device="cuda:0")
+    rbfdef.rbf_geom_volume_update(gctx, geom, w.radius, D, list(ref.level_off), to_dev(xc),
+                                  to_dev(ref.alpha), dv)
+    torch.cuda.synchronize()
+    got = dv.cpu().numpy()
+    want = orc.volume(w.radius, D, ref.level_off, xc, ref.alpha, w.xv, w.dwall)
+    scale = np.sqrt((want ** 2).sum(0)).max()
+    S = sum_magnitude(orc, w.radius, ref.level_off, xc, ref.alpha, w.xv, w.dwall, D)
+    err = np.sqrt(((got - want) ** 2).sum(0)).max()
+    assert err <= fp64_bound(scale, S)
+    far = w.dwall >= max(D)
+    assert np.all(got[:, far] == 0.0) and not np.any(np.signbit(got[:, far]))
+    rbfdef.rbf_geom_release(gctx, geom)
