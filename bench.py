@@ -46,6 +46,10 @@ def build_workload(name):
     if name == "cfg2":
         return synth.workload_cfg2(), ("3D swept wing ice horn: N_s=80000, N_v=4000000, R_l=3c/0.8c/0.2c, "
                                        "eps=1e-4c, cap 4000, D=1c")
+    if name == "cfg4":
+        return None, ("serving mix: 64 geometries (60% 2D airfoils, N_s 500-8000; 40% 3D wings, "
+                      "N_s 10k-80k), 4 warm-started icing steps each, Poisson arrivals at 20/s, "
+                      "eps in {1e-4, 1e-5}, mixed precision")
     if name == "cfg3":
         return synth.workload_cfg3(), ("3D swept wing bend+twist: N_s=80000, N_v=4000000, "
                                        "R_l=3c/0.8c/0.2c, eps=1e-4c, cap 4000, D=1c")
@@ -97,6 +101,78 @@ def cpu_baseline(w, ref, budget_s=12.0):
                       f"oracle control points, {reps} repetitions in {t:.1f} s"}
 
 
+def serving_replay(ctx, geoms, reqs, time_scale=1.0, compare=True):
+    """Replay a request mix through the serving loop: every geometry made resident first, each
+    request's surface displacement uploaded before the clock starts, then submissions at their
+    Poisson arrival times (later icing steps of a geometry warm-started from the previous one).
+    Latency = completion - arrival, both taken by the library's clock. With compare=True the same
+    requests also run one after another on the plain calls (greedy from scratch in FP64, then the
+    volume update with its per-call reduction), as a caller without the serving loop would."""
+    import numpy as np
+    import torch
+
+    from paper_2107_13887_amd import rbfdef
+
+    dev = torch.device("cuda:0")
+    steps = max(r.step for r in reqs)
+    handles, dvs, dss = [], [], []
+    for g in geoms:
+        handles.append(rbfdef.rbf_geom_create(ctx, torch.from_numpy(g.xs).to(dev),
+                                              torch.from_numpy(g.xv).to(dev),
+                                              torch.from_numpy(g.dwall).to(dev)))
+        dvs.append(torch.zeros((g.dim, g.xv.shape[1]), dtype=torch.float64, device=dev))
+    for r in reqs:
+        g = geoms[r.geom]
+        dss.append(torch.from_numpy(np.ascontiguousarray(g.shape * (r.step / steps))).to(dev))
+    torch.cuda.synchronize()
+    pend = []
+    t0 = rbfdef.rbf_now()
+    for r, ds in zip(reqs, dss):
+        g = geoms[r.geom]
+        wait = t0 + r.arrival * time_scale - rbfdef.rbf_now()
+        if wait > 0:
+            time.sleep(wait)
+        pend.append(rbfdef.rbf_submit(ctx, handles[r.geom], ds, dvs[r.geom], g.radius, r.eps,
+                                      [g.D] * len(g.radius), rho=0.1, cap=g.cap, precision=r.precision,
+                                      warm_start=r.step > 1))
+    infos = [rbfdef.rbf_wait(ctx, q) for q in pend]
+    t_end = max(i.t_done for i in infos)
+    failed = sum(1 for i in infos if i.state != rbfdef.REQ_DONE)
+    lat = sorted((i.t_done - i.t_arrive) * 1e3 for i in infos)
+    queue = sorted((i.t_start - i.t_arrive) * 1e3 for i in infos)
+    service = [(i.t_done - i.t_start) * 1e3 for i in infos]
+    pct = lambda v, q: v[min(len(v) - 1, int(q * len(v)))]
+    out = {
+        "requests": len(reqs), "geometries": len(geoms), "icing_steps": steps, "failed": failed,
+        "arrival_rate_per_s": len(reqs) / (reqs[-1].arrival * time_scale) if reqs[-1].arrival > 0 else None,
+        "p50_latency_ms": pct(lat, 0.50), "p99_latency_ms": pct(lat, 0.99),
+        "p50_queue_ms": pct(queue, 0.50), "mean_service_ms": statistics.mean(service),
+        "throughput_req_per_s": len(reqs) / (t_end - t0),
+        "makespan_s": t_end - t0,
+        "surface_points": sum(g.xs.shape[1] for g in geoms),
+        "volume_points": sum(g.xv.shape[1] for g in geoms),
+    }
+    for h in handles:
+        rbfdef.rbf_geom_release(ctx, h)
+    if compare:
+        stream = torch.cuda.current_stream()
+        dev_geom = [(torch.from_numpy(g.xs).to(dev), torch.from_numpy(g.xv).to(dev),
+                     torch.from_numpy(g.dwall).to(dev)) for g in geoms]
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for r, ds in zip(reqs, dss):
+            g = geoms[r.geom]
+            xs, xv, dw = dev_geom[r.geom]
+            cs = rbfdef.rbf_greedy_select(ctx, xs, ds, g.radius, r.eps, rho=0.1, cap=g.cap,
+                                          precision="fp64", want_residual=False)
+            rbfdef.rbf_volume_update(ctx, g.radius, [g.D] * len(g.radius), cs.level_off, cs.xc, cs.alpha,
+                                     xv, dw, precision="fp64")
+        torch.cuda.synchronize()
+        out["sequential_plain_fp64_s"] = time.perf_counter() - c0
+        out["sequential_plain_fp64_req_per_s"] = len(reqs) / out["sequential_plain_fp64_s"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +181,10 @@ def main():
     ap.add_argument("--workload", default="cfg1")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-geometries", type=int, default=16,
+                    help="geometries of the reduced serving mix replayed after the main timing (0: skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.25,
+                    help="size scale of the reduced serving mix")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -119,6 +199,8 @@ def main():
     import oracle
     from paper_2107_13887_amd import rbfdef
 
+    if args.workload == "cfg4":
+        return serve_main(args)
     t0 = time.perf_counter()
     w, desc = build_workload(args.workload)
     log(f"bench: workload {w.name} built in {time.perf_counter() - t0:.1f}s")
@@ -229,7 +311,60 @@ def main():
         "cpu_baseline": cpu,
     }
     rbfdef.rbf_geom_release(ctx, geom)
+    if args.serve_geometries > 0:
+        import synth
+
+        geoms, reqs = synth.serving_mix(n_geom=args.serve_geometries, scale=args.serve_scale)
+        log(f"bench: serving mix of {len(reqs)} requests on {len(geoms)} geometries")
+        srv = serving_replay(ctx, geoms, reqs)
+        srv["mix"] = (f"{args.serve_geometries} geometries at size scale {args.serve_scale} of the "
+                      "serving mix, 4 icing steps each, Poisson arrivals at 20/s, mixed precision")
+        rec["p50_latency_ms"] = srv["p50_latency_ms"]
+        rec["p99_latency_ms"] = srv["p99_latency_ms"]
+        rec["serving"] = srv
     rbfdef.rbf_ctx_destroy(ctx)
+    print(json.dumps(rec))
+
+
+def serve_main(args):
+    """The full serving mix: throughput and request latency through the serving loop."""
+    import torch
+
+    import synth
+    from paper_2107_13887_amd import rbfdef
+
+    t0 = time.perf_counter()
+    geoms, reqs = synth.serving_mix()
+    log(f"bench: serving mix built in {time.perf_counter() - t0:.1f}s")
+    ctx = rbfdef.rbf_ctx_create(0)
+    torch.cuda.synchronize()
+    # Warmup: one small replay compiles nothing but touches every code path and the pool.
+    wg, wr = synth.serving_mix(n_geom=4, scale=0.125, seed=9)
+    serving_replay(ctx, wg, wr, compare=False)
+    log("bench: warmup replay done")
+    srv = serving_replay(ctx, geoms, reqs)
+    rbfdef.rbf_ctx_destroy(ctx)
+    _, desc = build_workload("cfg4")
+    rec = {
+        "metric": "requests/s through the serving loop (p50/p99 request latency beside it)",
+        "value": srv["throughput_req_per_s"],
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": len(wr),
+        "ms_per_step": srv["makespan_s"] / len(reqs) * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"cfg4: {desc}", "parallelism": "single GPU"},
+        "p50_latency_ms": srv["p50_latency_ms"],
+        "p99_latency_ms": srv["p99_latency_ms"],
+        "serving": srv,
+        "roofline": None,
+        "cpu_baseline": None,
+    }
     print(json.dumps(rec))
 
 

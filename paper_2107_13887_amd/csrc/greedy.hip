@@ -24,6 +24,7 @@
 // equal the textbook formula term by term.
 #include <hip/hip_cooperative_groups.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -527,6 +528,146 @@ __global__ __launch_bounds__(256) void g_backsolve(const double *Lpack, double *
     }
 }
 
+// ---- warm start from a resident basis --------------------------------------------------------
+// Forward substitution L y = b for rows [b0, b1) of the packed factor (earlier rows done): every
+// workgroup solves the diagonal block, workgroup 0 stores y, and each removes the block's
+// contribution from its share of the rows below b1.
+template <int DIM>
+__global__ __launch_bounds__(256) void g_fwdsolve(const double *Lpack, double *b, int64_t ld_b,
+                                                  double *y, int64_t ld_y, int64_t n, int64_t b0, int64_t b1)
+{
+    __shared__ double Lb[64][65];
+    __shared__ double inv[64];
+    __shared__ double xb[DIM][64];
+    const int nb = (int)(b1 - b0);
+    for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x) {
+        const int r = t / 64, c = t % 64;
+        Lb[r][c] = (r < nb && c <= r) ? Lpack[((b0 + r) * (b0 + r + 1)) / 2 + b0 + c] : 0.0;
+    }
+    if (threadIdx.x < 64) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xb[k][threadIdx.x] = threadIdx.x < nb ? b[k * ld_b + b0 + threadIdx.x] : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int j = threadIdx.x;
+        inv[j] = j < nb ? 1.0 / Lb[j][j] : 0.0;
+        double rhs[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) rhs[k] = xb[k][j];
+        for (int i = 0; i < nb; ++i) {
+            const double ii = inv[i];
+            double xi[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) xi[k] = __shfl(rhs[k], i, 64) * ii;
+            if (j > i) {
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[j][i], xi[k], rhs[k]);
+            } else if (j == i) {
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) rhs[k] = xi[k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xb[k][j] = rhs[k];
+        if (blockIdx.x == 0 && j < nb) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) y[k * ld_y + b0 + j] = rhs[k];
+        }
+    }
+    __syncthreads();
+    for (int64_t r = b1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const double *row = Lpack + (r * (r + 1)) / 2 + b0;
+        double acc[DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) acc[k] = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            const double l = row[i];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) acc[k] = __builtin_fma(l, xb[k][i], acc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) b[k * ld_b + r] -= acc[k];
+    }
+}
+
+// b[k][j] = r[k][ctrl[j]] (the residual at the control points) and sel[ctrl[j]] = 1.
+template <int DIM>
+__global__ __launch_bounds__(256) void g_seed_rhs(const double *r, int64_t n_s, const int64_t *ctrl,
+                                                  int64_t n, double *b, int64_t ld_b, uint8_t *sel)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = ctrl[j];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) b[k * ld_b + j] = r[k * n_s + p];
+        sel[p] = 1;
+    }
+}
+
+// E = r - V y over all surface points for the n resident columns (Newton coefficients y in
+// coef), and the per-tile argmax of ||E_i||^2 over unselected points.
+template <int DIM>
+__global__ __launch_bounds__(NT) void g_apply(GArgs a, const double *r, int64_t n)
+{
+    __shared__ double ysh[DIM][LCHUNK / 2];
+    __shared__ double psum[UWAVES][DIM][UPB];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * UPB + lane;
+    const bool ok = i < a.n_s;
+    const int64_t ic = ok ? i : 0;
+    double s[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) s[k] = 0.0;
+    constexpr int CH = LCHUNK / 2;
+    for (int64_t j0 = 0; j0 < n; j0 += CH) {
+        const int nj = (int)min<int64_t>(CH, n - j0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nj; t += NT)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) ysh[k][t] = a.coef[k * a.ld_coef + j0 + t];
+        __syncthreads();
+        const int per = (nj + UWAVES - 1) / UWAVES;
+        const int jb = w * per, je = min(nj, jb + per);
+        for (int j = jb; j < je; ++j) {
+            const double v = a.V[(j0 + j) * a.n_s + ic];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) s[k] = __builtin_fma(v, ysh[k][j], s[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) psum[w][k][lane] = s[k];
+    __syncthreads();
+    if (w == 0) {
+        double m2 = -1.0;
+        int64_t idx = -1;
+        if (ok) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                double dot = psum[0][k][lane];
+                for (int q = 1; q < UWAVES; ++q) dot += psum[q][k][lane];
+                a.E[k * a.n_s + i] = r[k * a.n_s + i] - dot;
+            }
+            if (!a.sel[i]) {
+                m2 = norm2_plain<DIM>(a.E, a.n_s, i);
+                idx = i;
+            }
+        }
+        wave_argmax(m2, idx);
+        if (lane == 0) a.part[blockIdx.x] = Cand{m2, idx};
+    }
+}
+
+__global__ void g_set_count(GState *st, int64_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->n = n;
+        st->go = 0;
+        st->stop = -1;
+    }
+}
+
 template <int DIM>
 __global__ __launch_bounds__(256) void g_gather(const double *xs, int64_t n_s, const int64_t *ctrl,
                                                 int64_t n, double *xc, int64_t ld)
@@ -578,7 +719,8 @@ int cooperative_blocks(const void *kernel, int n_cu)
 
 template <int DIM>
 rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, const double *xs,
-                       const double *ds, rbf_ctrl_set *out, hipStream_t s)
+                       const double *ds, rbf_ctrl_set *out, hipStream_t s, const std::vector<LevelCache> *warm,
+                       std::vector<LevelCache> *store)
 {
     Pool *pool = ctx->pool.get();
     const int64_t cap = prm.max_ctrl_total;
@@ -672,6 +814,33 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         hipLaunchKernelGGL(g_begin, dim3(1), dim3(NT), 0, s, st, a.part, g, prm.eps_abs,
                            prm.level_reduction, (int32_t)(l == prm.n_levels - 1));
         RBF_HIP(hipGetLastError());
+        // Warm start from the resident basis of the same control points: copy V and L, then
+        // y = L^-1 r_C and E = r - V y; the level continues from n0 columns.
+        if (warm && l < (int)warm->size()) {
+            const LevelCache &lc = (*warm)[l];
+            const int64_t n0 = lc.n;
+            const bool same = n0 > 0 && n0 == a.n_seeds && lc.radius == Rl && n0 <= a.cap_level &&
+                              std::equal(lc.ctrl.begin(), lc.ctrl.end(), seeds_h.begin() + seed_off[l]);
+            if (same) {
+                RBF_HIP(hipMemcpyAsync(a.V, lc.V.ptr, sizeof(double) * n0 * n_s, hipMemcpyDeviceToDevice, s));
+                RBF_HIP(hipMemcpyAsync(a.Lpack, lc.L.ptr, sizeof(double) * (n0 * (n0 + 1) / 2),
+                                       hipMemcpyDeviceToDevice, s));
+                RBF_HIP(hipMemcpyAsync(a.ctrl, lc.ctrl.data(), sizeof(int64_t) * n0, hipMemcpyHostToDevice, s));
+                const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n0 + 255) / 256, 1024));
+                hipLaunchKernelGGL(g_seed_rhs<DIM>, dim3(gs), dim3(256), 0, s, R, n_s, a.ctrl, n0, R2, cols, a.sel);
+                for (int64_t b0 = 0; b0 < n0; b0 += 64) {
+                    const int64_t b1 = std::min<int64_t>(n0, b0 + 64);
+                    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n0 - b1 + 255) / 256, 1024));
+                    hipLaunchKernelGGL(g_fwdsolve<DIM>, dim3(gb), dim3(256), 0, s, a.Lpack, R2, cols, a.coef,
+                                       cols, n0, b0, b1);
+                }
+                hipLaunchKernelGGL(g_apply<DIM>, dim3((unsigned)g), dim3(NT), 0, s, a, (const double *)R, n0);
+                hipLaunchKernelGGL(g_set_count, dim3(1), dim3(64), 0, s, st, n0);
+                RBF_HIP(hipGetLastError());
+                a.n_seeds = 0;
+                a.max_iter = a.cap_level - n0 + 2;
+            }
+        }
         bool done = false;
         if (coop_max > 0) {
             const unsigned G = (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, coop_max));
@@ -756,6 +925,26 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
             RBF_TRY(run_kernel_sum(ctx, pb, s));
             std::swap(R, R2);
         }
+        if (store) {
+            if ((int)store->size() < prm.n_levels) store->resize(prm.n_levels);
+            LevelCache &lc = (*store)[l];
+            lc.V.release_after(s);
+            lc.L.release_after(s);
+            lc.n = 0;
+            if (n > 0 && lc.V.get(pool, sizeof(double) * n * n_s) == RBF_OK &&
+                lc.L.get(pool, sizeof(double) * (n * (n + 1) / 2)) == RBF_OK) {
+                RBF_HIP(hipMemcpyAsync(lc.V.ptr, a.V, sizeof(double) * n * n_s, hipMemcpyDeviceToDevice, s));
+                RBF_HIP(hipMemcpyAsync(lc.L.ptr, a.Lpack, sizeof(double) * (n * (n + 1) / 2),
+                                       hipMemcpyDeviceToDevice, s));
+                lc.ctrl.resize(n);
+                RBF_HIP(hipMemcpyAsync(lc.ctrl.data(), a.ctrl, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+                lc.n = n;
+                lc.radius = Rl;
+            } else {
+                lc.V.release_after(s);   // no room for this level's copy: leave it uncached
+                lc.L.release_after(s);
+            }
+        }
         total += n;
         out->level_off[l + 1] = (int32_t)total;
         used = l + 1;
@@ -770,6 +959,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         if (std::sqrt(hs.rmax2) < prm.eps_abs || out->level_stop[l] == RBF_STOP_CAP) break;
     }
     for (int l = used; l < prm.n_levels; ++l) out->level_off[l + 1] = (int32_t)total;
+    if (store)
+        for (int l = used; l < (int)store->size(); ++l) (*store)[l].n = 0;
     out->n_levels_used = used;
     out->stop_reason = out->level_stop[used - 1];
     out->n_iterations = hs.n_iter;
@@ -787,10 +978,19 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
 }  // namespace
 
 rbf_status run_greedy(rbf_ctx ctx, const rbf_greedy_params &p, int64_t n_s, const double *xs,
-                      const double *ds, rbf_ctrl_set *out, hipStream_t s)
+                      const double *ds, rbf_ctrl_set *out, hipStream_t s, const std::vector<LevelCache> *warm,
+                      std::vector<LevelCache> *store)
 {
-    return p.dim == 2 ? greedy_impl<2>(ctx, p, n_s, xs, ds, out, s)
-                      : greedy_impl<3>(ctx, p, n_s, xs, ds, out, s);
+    return p.dim == 2 ? greedy_impl<2>(ctx, p, n_s, xs, ds, out, s, warm, store)
+                      : greedy_impl<3>(ctx, p, n_s, xs, ds, out, s, warm, store);
+}
+
+uint64_t cache_bytes(const std::vector<LevelCache> &levels, int64_t n_s)
+{
+    uint64_t b = 0;
+    for (const LevelCache &lc : levels)
+        if (lc.n > 0) b += sizeof(double) * ((uint64_t)lc.n * n_s + (uint64_t)(lc.n * (lc.n + 1) / 2));
+    return b;
 }
 
 }  // namespace rbf

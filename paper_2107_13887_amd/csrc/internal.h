@@ -91,6 +91,17 @@ struct DevBuf {
 
 class Server;   // serving loop (serve.cpp)
 
+// Newton basis and Cholesky factor of one greedy level, kept between requests on a geometry:
+// V is [n][n_s] (column j = basis function j at every surface point), L is packed lower
+// (row j at j (j + 1) / 2). They depend on the geometry, the radius and the control points only,
+// so the next icing step warm-started from the same control points reuses them as they are.
+struct LevelCache {
+    DevBuf V, L;
+    int64_t n = 0;          // control points (columns)
+    double radius = 0.0;
+    std::vector<int64_t> ctrl;   // host copy, selection order
+};
+
 struct Geometry {
     int32_t dim = 0;
     int64_t n_s = 0, n_v = 0;
@@ -100,6 +111,9 @@ struct Geometry {
     int shift = 0;
     // Control sets of the last finished request (warm start), host copies per level.
     std::vector<std::vector<int64_t>> last_ctrl;
+    std::vector<LevelCache> levels;   // resident Newton bases of the last finished request
+    uint64_t cache_bytes = 0;         // device bytes held by `levels`
+    double last_use = 0.0;
     int32_t refs = 0;        // queued or running requests (guarded by the server's lock)
     bool running = false;    // a request on this geometry is running
     uint64_t bytes = 0;
@@ -174,8 +188,15 @@ struct SumProblem {
 rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s);
 
 // ---- greedy (greedy.hip) ------------------------------------------------------------------------
+// warm (optional): per-level resident Newton bases; a level whose seeds equal the cached control
+// points (same radius) starts from the cached basis instead of re-appending the seeds.
+// store (optional): receives every level's basis after the call (best effort: a level whose copy
+// cannot be allocated is left empty).
 rbf_status run_greedy(rbf_ctx ctx, const rbf_greedy_params &p, int64_t n_s, const double *xs,
-                      const double *ds, rbf_ctrl_set *out, hipStream_t s);
+                      const double *ds, rbf_ctrl_set *out, hipStream_t s,
+                      const std::vector<LevelCache> *warm = nullptr,
+                      std::vector<LevelCache> *store = nullptr);
+uint64_t cache_bytes(const std::vector<LevelCache> &levels, int64_t n_s);
 
 // ---- dense solves (chol.hip) --------------------------------------------------------------------
 rbf_status run_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c,

@@ -221,7 +221,7 @@ int64_t prefix_for(const Geometry &g, double D)
 uint64_t greedy_footprint(int dim, int64_t n_s, int64_t cap)
 {
     const uint64_t cols = (uint64_t)std::min<int64_t>(n_s, cap);
-    return sizeof(double) * (cols * (uint64_t)n_s + cols * (cols + 1) / 2 + (uint64_t)(3 * dim + 1) * n_s +
+    return sizeof(double) * (2 * (cols * (uint64_t)n_s + cols * (cols + 1) / 2) + (uint64_t)(3 * dim + 1) * n_s +
                              (uint64_t)(dim + 1) * cols + 2 * (uint64_t)cap) +
            (uint64_t)n_s * 17 + sizeof(int64_t) * (uint64_t)cap + sizeof(double) * (uint64_t)cap * 2 * dim;
 }
@@ -322,7 +322,18 @@ class Server {
                 blocked.push_back(q->g);
                 continue;
             }
-            if (reserved_ + q->reserve > budget) return nullptr;
+            // Resident bases of idle geometries yield to an admitted request's working memory.
+            while (reserved_ + q->reserve + cache_total_ > budget) {
+                Geometry *victim = nullptr;
+                for (Geometry *o : cached_)
+                    if (o != q->g && !o->running && (!victim || o->last_use < victim->last_use)) victim = o;
+                if (!victim) break;
+                cache_total_ -= victim->cache_bytes;
+                victim->levels.clear();
+                victim->cache_bytes = 0;
+                cached_.erase(std::find(cached_.begin(), cached_.end(), victim));
+            }
+            if (reserved_ + q->reserve + cache_total_ > budget) return nullptr;
             queue_.erase(it);
             return q;
         }
@@ -361,6 +372,20 @@ class Server {
     }
 
     rbf_status run(Req &q, hipStream_t s);
+
+  public:
+    void keep_bases(Geometry &g, std::vector<LevelCache> &&fresh);
+    void forget(Geometry *g);
+
+  private:
+    uint64_t cache_limit() const
+    {
+        const char *e = getenv("RBF_CACHE_FRACTION");
+        const double f = e ? atof(e) : 0.4;
+        return (uint64_t)(f * (double)ctx_->pool->budget());
+    }
+    std::vector<Geometry *> cached_;
+    uint64_t cache_total_ = 0;
 
     rbf_ctx ctx_;
     std::mutex mu_;
@@ -416,7 +441,8 @@ rbf_status Server::run(Req &q, hipStream_t s)
         local.e_final = nullptr;
         cs = &local;
     }
-    rbf_status st = run_greedy(ctx_, p, g.n_s, g.xs.as<double>(), q.r.ds, cs, s);
+    std::vector<LevelCache> fresh;
+    rbf_status st = run_greedy(ctx_, p, g.n_s, g.xs.as<double>(), q.r.ds, cs, s, &g.levels, &fresh);
     if (st < 0) return st;
     // Volume update on the resident, wall-distance-ordered volume.
     SumProblem pb;
@@ -447,7 +473,48 @@ rbf_status Server::run(Req &q, hipStream_t s)
     g.last_ctrl.assign(p.n_levels, {});
     for (int l = 0; l < p.n_levels; ++l)
         g.last_ctrl[l].assign(all.begin() + cs->level_off[l], all.begin() + cs->level_off[l + 1]);
+    keep_bases(g, std::move(fresh));
     return st;
+}
+
+// Resident Newton bases share a slice of the budget: least recently used idle geometries give
+// theirs up first; a set that cannot fit is dropped (the next step then re-appends its seeds).
+void Server::keep_bases(Geometry &g, std::vector<LevelCache> &&fresh)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    const uint64_t need = cache_bytes(fresh, g.n_s);
+    cache_total_ -= g.cache_bytes;
+    g.levels.clear();
+    g.cache_bytes = 0;
+    const uint64_t limit = cache_limit();
+    while (cache_total_ + need > limit) {
+        Geometry *victim = nullptr;
+        for (Geometry *o : cached_)
+            if (o != &g && !o->running && o->cache_bytes > 0 && (!victim || o->last_use < victim->last_use))
+                victim = o;
+        if (!victim) break;
+        cache_total_ -= victim->cache_bytes;
+        victim->levels.clear();
+        victim->cache_bytes = 0;
+        cached_.erase(std::find(cached_.begin(), cached_.end(), victim));
+    }
+    if (need > 0 && cache_total_ + need <= limit) {
+        g.levels = std::move(fresh);
+        g.cache_bytes = need;
+        g.last_use = now_seconds();
+        cache_total_ += need;
+        if (std::find(cached_.begin(), cached_.end(), &g) == cached_.end()) cached_.push_back(&g);
+    } else {
+        cached_.erase(std::remove(cached_.begin(), cached_.end(), &g), cached_.end());
+    }
+}
+
+void Server::forget(Geometry *g)
+{
+    std::lock_guard<std::mutex> lk(mu_);
+    cache_total_ -= g->cache_bytes;
+    g->cache_bytes = 0;
+    cached_.erase(std::remove(cached_.begin(), cached_.end(), g), cached_.end());
 }
 
 void server_shutdown(rbf_ctx ctx)
@@ -543,6 +610,7 @@ rbf_status rbf_geom_release(rbf_ctx ctx, rbf_geom geom)
     if (it == ctx->geoms.end()) return fail(RBF_E_NOT_FOUND, "unknown geometry");
     if (ctx->server && ctx->server->geometry_busy(it->second.get()))
         return fail(RBF_E_BUSY, "geometry still has queued or running requests");
+    if (ctx->server) ctx->server->forget(it->second.get());
     ctx->geoms.erase(it);
     return RBF_OK;
 }

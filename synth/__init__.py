@@ -376,3 +376,87 @@ def random_workload(seed: int, dim: int, n_s: int, n_v: int, radius, eps: float,
     return Workload(f"random{seed}_d{dim}_s{n_s}", dim, xs, np.ascontiguousarray(ds), xv, dwall,
                     radius=list(radius), eps=eps, D=D, cap=cap, rho=rho,
                     seeds=seeds if seeds is not None else [[0]])
+
+
+# --------------------------------------------------------------------------------------------
+# Serving mix
+# --------------------------------------------------------------------------------------------
+@dataclass
+class MixGeometry:
+    dim: int
+    xs: np.ndarray
+    xv: np.ndarray
+    dwall: np.ndarray
+    normals: np.ndarray
+    shape: np.ndarray          # [dim, n_s] displacement of the final icing step
+    radius: List[float]
+    D: float
+    cap: int
+
+
+@dataclass
+class MixRequest:
+    geom: int                  # index into the geometry list
+    step: int                  # icing step 1..steps (amplitude step/steps)
+    arrival: float             # seconds after the start
+    eps: float
+    precision: str
+
+
+def serving_mix(n_geom: int = 64, steps: int = 4, rate: float = 20.0, frac_2d: float = 0.6,
+                scale: float = 1.0, precision: str = "mixed", seed: int = 4):
+    """Seeded request mix: 2D airfoils (surface log-uniform in [500, 8000] points, O-mesh with
+    40-100 layers) and 3D wings (400 x [25, 200] surface grid, 50 layers), each geometry deformed
+    in `steps` successive icing steps of growing amplitude (ice horns, or bending plus twist for
+    half of the wings), eps drawn from {1e-4, 1e-5}, Poisson arrivals at `rate` per second with
+    each geometry's steps in order. `scale` < 1 shrinks every surface and volume (tests, quick
+    runs)."""
+    rng = np.random.default_rng(SEED_BASE + seed)
+    geoms: List[MixGeometry] = []
+    n2 = int(round(frac_2d * n_geom))
+    for g in range(n_geom):
+        if g < n2:
+            n_s = int(np.exp(rng.uniform(np.log(500), np.log(8000))) * scale)
+            n_s = max(64, n_s - n_s % 2)
+            n_r = int(round(40 + 60 * np.log(max(n_s / scale, 500) / 500) / np.log(16)))
+            n_r = max(4, int(n_r * min(1.0, scale * 4)))
+            xs, xv = airfoil_2d(n_s, n_r, 1e-3)
+            nx, ny = contour_normals(xs[0], xs[1])
+            s = arc_length_from_te(xs[0], xs[1])
+            half = n_s // 2
+            amp = np.zeros(n_s)
+            for side in (0, 1):
+                xc = rng.uniform(0.005, 0.03)
+                s_up = upper_arc_length_at(xs[0], s, xc)
+                s_c = s_up if side == 0 else 2.0 * s[half] - s_up
+                amp += rng.uniform(0.02, 0.05) * _gauss(s, s_c, rng.uniform(0.01, 0.03))
+            amp += np.where(xs[0] < 0.1, 0.005, 0.0)
+            shape = np.stack([amp * nx, amp * ny])
+            geoms.append(MixGeometry(2, xs, xv, wall_distance(xs, xv), np.stack([nx, ny]), shape,
+                                     [2.0, 0.5, 0.1], 0.5, 3 * n_s))
+        else:
+            n_c = max(40, int(400 * scale) - int(400 * scale) % 2)
+            n_span = max(6, int(rng.integers(25, 201) * scale))
+            n_r = max(4, int(50 * min(1.0, scale * 4)))
+            xyz, vol, xc2, zc2, yk = wing_3d(n_c, n_span, n_r)
+            n = wing_normals(xyz, n_c, n_span)
+            if rng.uniform() < 0.5:
+                s = arc_length_from_te(xc2, zc2)
+                s0 = upper_arc_length_at(xc2, s, 0.01)
+                u = rng.uniform(-1.0, 1.0, size=n_span)
+                amp_k = 0.04 * (1.0 - 0.5 * yk / yk[-1]) * (1.0 + 0.1 * u)
+                shape = n * (amp_k[:, None] * _gauss(s, s0, 0.02)[None, :]).reshape(-1)[None, :]
+            else:
+                shape = bend_twist(xyz, yk[-1])
+            geoms.append(MixGeometry(3, xyz, vol, wall_distance(xyz, vol), n, np.ascontiguousarray(shape),
+                                     [3.0, 0.8, 0.2], 1.0, min(4000, xyz.shape[1])))
+    order = [g for g in range(n_geom) for _ in range(steps)]
+    rng.shuffle(order)
+    seen = [0] * n_geom
+    t = 0.0
+    reqs: List[MixRequest] = []
+    for g in order:
+        t += rng.exponential(1.0 / rate)
+        seen[g] += 1
+        reqs.append(MixRequest(g, seen[g], t, float(rng.choice([1e-4, 1e-5])), precision))
+    return geoms, reqs

@@ -192,3 +192,29 @@ def test_geom_volume_update_matches_oracle(gctx, orc):
     far = w.dwall >= max(D)
     assert np.all(got[:, far] == 0.0) and not np.any(np.signbit(got[:, far]))
     rbfdef.rbf_geom_release(gctx, geom)
+
+
+def test_warm_start_reuses_resident_basis(gctx):
+    """Three icing steps on one geometry with warm start: the steps after the first reuse the
+    resident Newton bases. A fresh geometry given the same sequence (first cold, then warm) gives
+    the same control sets and bit-identical displacements (the reuse is exact)."""
+    w = synth.workload_cfg1(n_s=600, n_layers=8)
+    runs = []
+    for rep in range(2):
+        geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
+        outs = []
+        for step in range(3):
+            ws = synth.Workload(w.name, 2, w.xs, np.ascontiguousarray((1.0 + 0.3 * step) * w.ds), w.xv,
+                                w.dwall, w.radius, w.eps, w.rho, w.D, w.cap, w.seeds)
+            dv = torch.zeros((2, w.n_v), dtype=torch.float64, device="cuda:0")
+            r = _submit(gctx, geom, ws, dv, warm=step > 0, want_ctrl=True)
+            info = rbfdef.rbf_wait(gctx, r)
+            assert info.state == rbfdef.REQ_DONE, info.result
+            outs.append((r.out.ctrl_idx[: r.out.total].cpu().numpy(), dv.clone()))
+        runs.append(outs)
+        rbfdef.rbf_geom_release(gctx, geom)
+    for (c1, d1), (c2, d2) in zip(*runs):
+        assert np.array_equal(c1, c2)
+        assert torch.equal(d1, d2)
+    # warm steps keep the earlier control points as their first ones
+    assert np.array_equal(runs[0][1][0][: len(runs[0][0][0])][:5], runs[0][0][0][:5])
