@@ -79,6 +79,10 @@ uint64_t rbf_ctx_bytes_in_use(rbf_ctx ctx);
  * and the number of launches since timing was last enabled; set_timing clears the totals. */
 rbf_status rbf_ctx_set_timing(rbf_ctx ctx, int32_t enabled);
 rbf_status rbf_ctx_kernel_time(rbf_ctx ctx, const char *kernel, double *total_ms, int64_t *launches);
+/* (point, control) pairs the named kernel sums actually evaluated since timing was last enabled:
+ * pairs whose control was dropped because its support misses the point's workgroup (phi = 0
+ * there, eq. (2)) are not counted. Waits for the device. */
+rbf_status rbf_ctx_kernel_pairs(rbf_ctx ctx, const char *kernel, int64_t *pairs);
 
 /* ---------------------------------------------------------------------------------------------
  * Greedy parameters (Section 3). The paper's defaults: one support radius R for all levels,
@@ -158,8 +162,11 @@ rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, in
 
 /* ---------------------------------------------------------------------------------------------
  * Serving: resident geometries and asynchronous deformation requests with continuous batching.
- * A geometry (surface + volume + wall distance) is copied once into the pool and kept, volume
- * sorted by wall distance so each request's reduced volume is a prefix. Requests that arrive
+ * A geometry (surface + volume + wall distance) is copied once into the pool and kept, the
+ * volume stored in spatially compact blocks of 512 points (Z order) sorted by their smallest wall
+ * distance, so each request's reduced volume lies in a prefix of whole blocks and each block can
+ * skip the controls whose support misses it. The device copy takes 8 (dim + 1) + 4 bytes per
+ * volume point (rounded up to whole blocks) plus 8 dim per surface point. Requests that arrive
  * while others run are admitted as soon as a slot and enough of the HBM budget are free; their
  * kernels overlap on separate streams. A request with warm_start seeds each level with the
  * control set the geometry's previous request selected (successive icing steps).
@@ -196,10 +203,10 @@ typedef struct {
     double t_done;
 } rbf_req_info;
 
-/* Volume update of eqs. (19) and (23) on a resident geometry: the volume is stored in
- * wall-distance order, so the reduced volume {d < max_l D_l} of section 4 is a prefix found from
- * the stored bin offsets (no per-call compaction). Arguments as rbf_volume_update; dv is
- * device [dim][n_v] in the geometry's original point order, fully written. Enqueued on stream. */
+/* Volume update of eqs. (19) and (23) on a resident geometry: the reduced volume {d < max_l D_l}
+ * of section 4 lies in the prefix of stored blocks whose smallest wall distance is below max_l
+ * D_l (no per-call compaction). Arguments as rbf_volume_update; dv is device [dim][n_v] in the
+ * geometry's original point order, fully written (+0.0 where psi = 0). Enqueued on stream. */
 rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, const double *radius,
                                   const double *D, const int32_t *level_off, int64_t ld_ctrl,
                                   const double *xc, const double *alpha, double *dv,

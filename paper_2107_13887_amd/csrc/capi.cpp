@@ -170,6 +170,23 @@ void KernelTimers::end(const char *name, hipEvent_t a, hipStream_t s)
     pending.push_back(Pending{name, a, b});
 }
 
+unsigned long long *KernelTimers::counter(const char *name)
+{
+    std::lock_guard<std::mutex> lk(mu);
+    if (!enabled || !dev_count) return nullptr;
+    auto it = slot.find(name);
+    if (it == slot.end()) {
+        if ((int)slot.size() >= N_COUNT) return nullptr;
+        it = slot.emplace(name, (int)slot.size()).first;
+    }
+    return dev_count + it->second;
+}
+
+KernelTimers::~KernelTimers()
+{
+    if (dev_count) (void)hipFree(dev_count);
+}
+
 void KernelTimers::resolve()
 {
     std::lock_guard<std::mutex> lk(mu);
@@ -291,9 +308,32 @@ rbf_status rbf_ctx_set_timing(rbf_ctx ctx, int32_t enabled)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
     ctx->timers.resolve();
+    RBF_HIP(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> lk(ctx->timers.mu);
     ctx->timers.enabled = enabled != 0;
     ctx->timers.total.clear();
+    if (enabled && !ctx->timers.dev_count)
+        RBF_HIP(hipMalloc((void **)&ctx->timers.dev_count, sizeof(unsigned long long) * KernelTimers::N_COUNT));
+    if (ctx->timers.dev_count) {
+        RBF_HIP(hipDeviceSynchronize());
+        RBF_HIP(hipMemset(ctx->timers.dev_count, 0, sizeof(unsigned long long) * KernelTimers::N_COUNT));
+    }
+    return RBF_OK;
+}
+
+rbf_status rbf_ctx_kernel_pairs(rbf_ctx ctx, const char *kernel, int64_t *pairs)
+{
+    if (!ctx || !kernel || !pairs) return fail(RBF_E_INVALID, "NULL argument");
+    ctx->timers.resolve();
+    RBF_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(ctx->timers.mu);
+    *pairs = 0;
+    auto it = ctx->timers.slot.find(kernel);
+    if (it == ctx->timers.slot.end() || !ctx->timers.dev_count) return RBF_OK;
+    RBF_HIP(hipDeviceSynchronize());
+    unsigned long long v = 0;
+    RBF_HIP(hipMemcpy(&v, ctx->timers.dev_count + it->second, sizeof v, hipMemcpyDeviceToHost));
+    *pairs = (int64_t)v;
     return RBF_OK;
 }
 

@@ -105,10 +105,11 @@ struct LevelCache {
 struct Geometry {
     int32_t dim = 0;
     int64_t n_s = 0, n_v = 0;
-    DevBuf xs, xv_sorted, d_sorted, perm;   // volume in wall-distance order, perm: stored -> caller
-    std::vector<int32_t> bin_off;           // host: start of each wall-distance bin, plus n_v
-    uint64_t lo_bits = 0;                   // bin(d) = (bits(d) - lo_bits) >> shift
-    int shift = 0;
+    // Volume stored in blocks of VBLOCK Z-ordered points, blocks by increasing smallest wall
+    // distance; n_pad = whole blocks, padding slots have perm -1 and d = +inf.
+    DevBuf xs, xv_sorted, d_sorted, perm;   // perm: stored slot -> caller's index
+    int64_t n_pad = 0;
+    std::vector<double> block_dmin;         // host: smallest wall distance of each stored block
     // Control sets of the last finished request (warm start), host copies per level.
     std::vector<std::vector<int64_t>> last_ctrl;
     std::vector<LevelCache> levels;   // resident Newton bases of the last finished request
@@ -129,9 +130,15 @@ struct KernelTimers {
     struct Pending { std::string name; hipEvent_t a, b; };
     std::vector<Pending> pending;
     std::map<std::string, std::pair<double, int64_t>> total;   // name -> (ms, launches)
+    // Evaluated-pair counters of the kernel sums, one device slot per timed kernel name.
+    static constexpr int N_COUNT = 16;
+    unsigned long long *dev_count = nullptr;
+    std::map<std::string, int> slot;
     void begin(hipEvent_t *a, hipStream_t s);
     void end(const char *name, hipEvent_t a, hipStream_t s);
     void resolve();
+    unsigned long long *counter(const char *name);   // null while timing is off
+    ~KernelTimers();
 };
 }  // namespace rbf
 
@@ -155,6 +162,9 @@ struct rbf_geom_s {};  // opaque handle; the address keys the context's geometry
 namespace rbf {
 
 // ---- kernel sums (ksum.hip) ---------------------------------------------------------------------
+// Points per stored volume block: one kernel-sum workgroup (256 lanes x 2 points).
+constexpr int VBLOCK = 512;
+
 struct SumLevel {
     double inv_r;     // 1 / R_l
     double D;         // wall-distance support D_l, or 0 when psi is not applied
@@ -174,11 +184,13 @@ struct SumProblem {
     const double *dwall = nullptr;  // [n_p] or null (psi = 1)
     const double *base = nullptr;   // out = base - sign * sum (base null: 0)
     double sign = -1.0;
-    double *out = nullptr;        // [dim][n_p], fully written
+    double *out = nullptr;        // [dim][ld_out], fully written
+    int64_t ld_out = 0;           // 0: n_p
     int32_t precision = RBF_FP64;
-    // Resident geometry: points (xp, dwall) are stored in wall-distance order, the reduced volume
-    // is the prefix [0, n_active), and result v goes to out[.][perm[v]] (perm: stored -> caller
-    // order); points beyond the prefix get +0.0 through perm. n_active < 0: not used.
+    // Resident geometry: points (xp, dwall) are stored in blocks ordered by their smallest wall
+    // distance, the reduced volume lies in the prefix [0, n_active), and the result of slot v goes
+    // to out[.][perm[v]] (perm: stored -> caller order, -1 for padding); points with psi = 0 get
+    // +0.0 through perm. n_active < 0: not used.
     const int32_t *perm = nullptr;
     int64_t n_active = -1;
 };

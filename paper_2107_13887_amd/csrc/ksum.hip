@@ -11,9 +11,15 @@
 //     same LDS address, a broadcast without bank conflicts;
 //   * the control list of each level may be split over gridDim.y so that few points still give
 //     enough waves; split partial sums are reduced in a fixed order (deterministic results);
+//   * compact support: each workgroup takes the bounding box of its points that any level
+//     weights, and while a control tile is staged every control whose distance to that box is at
+//     least R_l (with a relative margin of 1e-4) is dropped by a stable in-tile compaction, so
+//     the pair loop runs over the controls that can reach the workgroup only. Dropped pairs
+//     have phi = 0 exactly, and the order of the kept ones is unchanged, so the sums equal the
+//     uncut ones;
 //   * the wall-distance reduction keeps only points with d < max_l D_l: the prefix of a resident
-//     volume stored in wall-distance order, or a stable two-kernel compaction that also writes
-//     +0.0 to every dropped point;
+//     volume stored in spatially compact blocks ordered by their smallest wall distance, or a
+//     stable two-kernel compaction that also writes +0.0 to every dropped point;
 //   * FP64 square root from the hardware reciprocal square-root estimate e refined by one
 //     Goldschmidt step (error ~1.5 e^2) and one Newton correction (error ~1.5 e^3);
 //   * mixed precision: the pair arithmetic runs in FP32 on coordinates shifted to a per-workgroup
@@ -34,7 +40,7 @@ struct KArgs {
     const double *alpha;            // [DIM][ld_ctrl]
     int64_t ld_ctrl;
     const int32_t *work;            // reduced point list, or null for the identity
-    const int32_t *out_perm;        // resident geometry: output index of stored point w
+    const int32_t *out_perm;        // resident geometry: output index of stored point w (-1: padding)
     const int64_t *n_work_dev;      // device-side count (null: use n_work)
     int64_t n_work;
     const double *xp;
@@ -46,7 +52,14 @@ struct KArgs {
     int64_t ld_out;
     double *partial;                // [n_split][DIM][ld_part]
     int64_t ld_part;
+    double dmax;                    // max_l D_l (points at or beyond it take no part in any level)
+    unsigned long long *pairs;      // evaluated (point, control) pairs are added here, or null
 };
+
+// A control is dropped for a workgroup when its squared distance to the workgroup's box, in units
+// of R_l, is at least (1 + 1e-4)^2: every pair it would form then has eta > 1 and phi = 0, with
+// room for the rounding of the scaled coordinates (FP64, or FP32 on shifted coordinates).
+constexpr double CULL2 = 1.00020001;
 
 __device__ __forceinline__ double sqrt_goldschmidt(double a)
 {
@@ -116,9 +129,13 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
     // scaled coordinates (two doubles' room), then DIM weights in FP64.
     constexpr int ST = MIXED ? (2 + DIM) : 2 * DIM;     // doubles per control in LDS
     constexpr int AOFF = MIXED ? 2 : DIM;               // offset of the weights
+    constexpr int NW = BLOCK / 64;                      // waves per workgroup
     __shared__ double tile[TILE * ST];
     __shared__ double origin[DIM];
-    const int tid = threadIdx.x;
+    __shared__ double wbox[NW][2 * DIM];
+    __shared__ double box[2 * DIM];                     // workgroup box: min[DIM], max[DIM]
+    __shared__ int wcnt[NW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n_work = a.n_work_dev ? *a.n_work_dev : a.n_work;
     const int64_t wbase = (int64_t)blockIdx.x * (BLOCK * P);
     if (wbase >= n_work) return;
@@ -126,7 +143,14 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
 
     int64_t idx[P];
     bool ok[P];
-    double dw[P], acc[P][DIM];
+    double dw[P], acc[P][DIM], xq[P][DIM];
+    double lo[DIM], hi[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        lo[k] = HUGE_VAL;
+        hi[k] = -HUGE_VAL;
+    }
+    // Every load of the point data is issued up front; the coordinates stay in registers.
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int64_t w = wbase + p * BLOCK + tid;
@@ -134,16 +158,50 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
         idx[p] = ok[p] ? (a.work ? (int64_t)a.work[w] : w) : 0;
         dw[p] = (a.dwall && ok[p]) ? a.dwall[idx[p]] : 0.0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) acc[p][k] = 0.0;
-    }
-    if (MIXED) {
-        if (tid == 0) {
-            const int64_t i0 = a.work ? (int64_t)a.work[wbase] : wbase;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) origin[k] = a.xp[k * a.ld_p + i0];
+        for (int k = 0; k < DIM; ++k) {
+            xq[p][k] = a.xp[k * a.ld_p + idx[p]];
+            acc[p][k] = 0.0;
         }
-        __syncthreads();
     }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        // Box of the points some level weights (psi > 0 needs d < max_l D_l).
+        if (ok[p] && (!a.dwall || dw[p] < a.dmax)) {
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                lo[k] = fmin(lo[k], xq[p][k]);
+                hi[k] = fmax(hi[k], xq[p][k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
+        }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            wbox[wave][k] = lo[k];
+            wbox[wave][DIM + k] = hi[k];
+        }
+    if (MIXED && tid == 0) {
+        const int64_t i0 = a.work ? (int64_t)a.work[wbase] : wbase;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) origin[k] = a.xp[k * a.ld_p + i0];
+    }
+    __syncthreads();
+    if (tid < 2 * DIM) {
+        double v = wbox[0][tid];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) v = tid < DIM ? fmin(v, wbox[w][tid]) : fmax(v, wbox[w][tid]);
+        box[tid] = v;
+    }
+    __syncthreads();
+    const int64_t n_valid = min<int64_t>(BLOCK * P, n_work - wbase);
+    unsigned long long n_eval = 0;
 
     for (int l = 0; l < a.n_levels; ++l) {
         double wg[P];
@@ -164,28 +222,56 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                const double x = a.xp[k * a.ld_p + idx[p]];
-                if (MIXED) q32[p][k] = (float)((x - origin[k]) * inv_r);
-                else q64[p][k] = x * inv_r;
+                if (MIXED) q32[p][k] = (float)((xq[p][k] - origin[k]) * inv_r);
+                else q64[p][k] = xq[p][k] * inv_r;
                 la[p][k] = 0.0;
             }
         for (int64_t t0 = cb; t0 < ce; t0 += TILE) {
             const int nt = (int)min<int64_t>(TILE, ce - t0);
             __syncthreads();
+            // Stage the tile: keep the controls whose support reaches the box, in order.
+            double xck[DIM], ack[DIM];
+            bool keep = false;
             if (tid < nt) {
-                double *dst = tile + tid * ST;
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
-                    const double xck = a.xc[k * a.ld_ctrl + t0 + tid];
-                    if (MIXED) reinterpret_cast<float *>(dst)[k] = (float)((xck - origin[k]) * inv_r);
-                    else dst[k] = xck * inv_r;
+                    xck[k] = a.xc[k * a.ld_ctrl + t0 + tid];
+                    ack[k] = a.alpha[k * a.ld_ctrl + t0 + tid];
+                }
+                double g2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    const double c = xck[k] * inv_r;
+                    const double gap = fmax(fmax(box[k] * inv_r - c, c - box[DIM + k] * inv_r), 0.0);
+                    g2 = __builtin_fma(gap, gap, g2);
+                }
+                keep = g2 < CULL2;
+            }
+            const unsigned long long m = __ballot(keep);
+            if (lane == 0) wcnt[wave] = __popcll(m);
+            __syncthreads();
+            int pos = __popcll(m & ((1ull << lane) - 1ull));
+            int kept = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                pos += w < wave ? wcnt[w] : 0;
+                kept += wcnt[w];
+            }
+            kept = __builtin_amdgcn_readfirstlane(kept);   // the same in every lane: a scalar loop bound
+            if (keep) {
+                double *dst = tile + pos * ST;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    if (MIXED) reinterpret_cast<float *>(dst)[k] = (float)((xck[k] - origin[k]) * inv_r);
+                    else dst[k] = xck[k] * inv_r;
                 }
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) dst[AOFF + k] = a.alpha[k * a.ld_ctrl + t0 + tid];
+                for (int k = 0; k < DIM; ++k) dst[AOFF + k] = ack[k];
             }
             __syncthreads();
+            n_eval += (unsigned long long)kept;
 #pragma unroll 2
-            for (int c = 0; c < nt; ++c) {
+            for (int c = 0; c < kept; ++c) {
                 const double *cc = tile + c * ST;
                 double cal[DIM];
 #pragma unroll
@@ -218,12 +304,14 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
 #pragma unroll
             for (int k = 0; k < DIM; ++k) acc[p][k] = __builtin_fma(wg[p], la[p][k], acc[p][k]);
     }
+    if (a.pairs && tid == 0 && n_eval) atomicAdd(a.pairs, n_eval * (unsigned long long)n_valid);
 
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         if (!ok[p]) continue;
         if (a.n_split == 1) {
             const int64_t oi = a.out_perm ? (int64_t)a.out_perm[idx[p]] : idx[p];
+            if (oi < 0) continue;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
                 const int64_t o = k * a.ld_out + oi;
@@ -247,6 +335,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_finalize(KArgs a)
          w += (int64_t)gridDim.x * BLOCK) {
         const int64_t idx = a.work ? (int64_t)a.work[w] : w;
         const int64_t oi = a.out_perm ? (int64_t)a.out_perm[idx] : idx;
+        if (oi < 0) continue;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             double s = 0.0;
@@ -374,7 +463,8 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     a.base = pb.base;
     a.sign = pb.sign;
     a.out = pb.out;
-    a.ld_out = pb.n_p;
+    a.ld_out = pb.ld_out ? pb.ld_out : pb.n_p;
+    a.dmax = dmax;
     a.n_work = pb.n_p;
 
     DevBuf work, nwork, partial, counts;
@@ -403,7 +493,10 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
 
     // Launch shape: P points per lane; split the control lists when there are too few blocks.
     const bool mixed = pb.precision == RBF_MIXED;
-    int P = env_int("RBF_KSUM_P", 2);
+    // Two points per lane share every control read from LDS; one point per lane gives twice the
+    // workgroups, which balances better when there are few blocks (the cost of a block varies
+    // with the number of controls near it).
+    int P = env_int("RBF_KSUM_P", n_rows < (int64_t)8 * ctx->n_cu * VBLOCK ? 1 : 2);
     if (P != 1 && P != 2 && P != 4) P = 2;
     const int64_t nbx = (n_rows + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
     const int64_t target = (int64_t)env_int("RBF_KSUM_BLOCKS", 8 * ctx->n_cu);
@@ -419,13 +512,15 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
         a.ld_part = n_rows;
     }
     const dim3 grid((unsigned)nbx, (unsigned)S);
+    const char *name = pb.dwall ? (mixed ? "volume_ksum_mixed" : "volume_ksum_fp64")
+                                : (mixed ? "surface_ksum_mixed" : "surface_ksum_fp64");
+    a.pairs = ctx->timers.counter(name);
     hipEvent_t t0;
     ctx->timers.begin(&t0, s);
     if (DIM == 2) launch_sum_p<2>(a, grid, P, mixed, s);
     else launch_sum_p<3>(a, grid, P, mixed, s);
     RBF_HIP(hipGetLastError());
-    ctx->timers.end(pb.dwall ? (mixed ? "volume_ksum_mixed" : "volume_ksum_fp64")
-                             : (mixed ? "surface_ksum_mixed" : "surface_ksum_fp64"), t0, s);
+    ctx->timers.end(name, t0, s);
     if (S > 1) {
         const int gf = (int)std::min<int64_t>((n_rows + BLOCK - 1) / BLOCK, 8192);
         if (DIM == 2) hipLaunchKernelGGL(ksum_finalize<2>, dim3(gf), dim3(BLOCK), 0, s, a);

@@ -2,10 +2,13 @@
 //
 // Geometry. rbf_geom_create copies the surface and volume into the context's pool, computes the
 // wall distance when none is given (distance to the nearest surface point), and stores the volume
-// in wall-distance order: a stable counting sort over bins taken from the FP64 bit pattern of d
-// (exactly monotone in d, roughly logarithmic). The reduced volume of any request, {d < max D_l},
-// is then a prefix whose end the host knows from the bin offsets (section 4's volume point
-// reduction without any per-request compaction); results go back through the permutation.
+// in blocks of VBLOCK points: the points are put in Z order (a space-filling curve over the
+// bounding box, so each block is spatially compact), cut into blocks, and the blocks are stored
+// by increasing smallest wall distance. The reduced volume of any request, {d < max D_l} (section
+// 4), is then inside a prefix of whole blocks whose end the host knows from the sorted block
+// minima, with no per-request compaction; and every kernel-sum workgroup takes one compact block,
+// which lets it skip the controls whose support misses the block. Results go back through the
+// permutation.
 //
 // Requests. rbf_submit copies the request and queues it. Worker slots, each with its own HIP
 // stream, pull requests in arrival order as soon as they are free: a request is admitted when its
@@ -22,24 +25,8 @@
 namespace rbf {
 namespace {
 
-constexpr int NBIN = 1024;
-constexpr int SORT_BLK = 2048;
-
-__device__ __host__ inline uint64_t dbits(double d)
-{
-    uint64_t u;
-    memcpy(&u, &d, sizeof u);
-    return u;
-}
-
-// Bin of a non-negative distance: (bits(d) - bits(lo)) >> shift, clamped. Monotone in d.
-__device__ __host__ inline int dist_bin(double d, uint64_t lo_bits, int shift)
-{
-    const uint64_t b = dbits(d);
-    if (b <= lo_bits) return 0;
-    const uint64_t k = (b - lo_bits) >> shift;
-    return k >= (uint64_t)NBIN ? NBIN - 1 : (int)k;
-}
+constexpr int SORT_BLK = 2048;    // points per workgroup in the radix passes
+constexpr int NBUCKET = 256;      // 8-bit digits
 
 // d_v = min_s ||x_v - x_s|| over the surface points (surface staged through LDS).
 template <int DIM>
@@ -72,39 +59,107 @@ __global__ __launch_bounds__(256) void geo_walldist(const double *xs, int64_t n_
     if (v < n_v) d[v] = sqrt(best);
 }
 
-__global__ __launch_bounds__(256) void geo_minmax(const double *d, int64_t n, unsigned long long *mm)
+// Per-workgroup bounding boxes of the volume: part[blockIdx][0..DIM) = min, [DIM..2 DIM) = max.
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_bbox(const double *xv, int64_t n, double *part)
 {
-    // mm[0] = bits of the smallest positive distance, mm[1] = bits of the largest (exact).
-    unsigned long long lo = ~0ull, hi = 0ull;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const unsigned long long b = dbits(d[i]);
-        if (d[i] > 0.0 && b < lo) lo = b;
-        if (b > hi) hi = b;
+    __shared__ double red[256][2 * DIM];
+    double lo[DIM], hi[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        lo[k] = HUGE_VAL;
+        hi[k] = -HUGE_VAL;
     }
-    atomicMin(&mm[0], lo);
-    atomicMax(&mm[1], hi);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            lo[k] = fmin(lo[k], xv[k * n + i]);
+            hi[k] = fmax(hi[k], xv[k * n + i]);
+        }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        red[threadIdx.x][k] = lo[k];
+        red[threadIdx.x][DIM + k] = hi[k];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                red[threadIdx.x][k] = fmin(red[threadIdx.x][k], red[threadIdx.x + s][k]);
+                red[threadIdx.x][DIM + k] = fmax(red[threadIdx.x][DIM + k], red[threadIdx.x + s][DIM + k]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2 * DIM) part[blockIdx.x * 2 * DIM + threadIdx.x] = red[0][threadIdx.x];
 }
 
-// Per-block bin histograms, stored bin-major: hist[bin * nblk + block].
-__global__ __launch_bounds__(256) void geo_hist(const double *d, int64_t n, uint64_t lo_bits, int shift,
-                                                int32_t *hist, int64_t nblk)
+// Spread the low bits of v so that consecutive bits land DIM positions apart (bit interleaving
+// for a Z-order key).
+__device__ inline uint32_t spread2(uint32_t v)
 {
-    __shared__ int32_t h[NBIN];
-    for (int b = threadIdx.x; b < NBIN; b += 256) h[b] = 0;
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+__device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+struct Box {
+    double lo[3];
+    double scale[3];   // cells per unit length
+};
+
+// Z-order key of every volume point on a 2^16 x 2^16 (2D) or 2^10 x 2^10 x 2^10 (3D) grid over
+// the bounding box; idx = the point's index.
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_morton(const double *xv, int64_t n, Box box, uint32_t *key,
+                                                  int32_t *idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    constexpr double top = DIM == 2 ? 65535.0 : 1023.0;
+    uint32_t q[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) q[k] = (uint32_t)fmin(top, fmax(0.0, (xv[k * n + i] - box.lo[k]) * box.scale[k]));
+    uint32_t m = 0;
+    if (DIM == 2) m = spread2(q[0]) | (spread2(q[1]) << 1);
+    else m = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[DIM - 1]) << 2);
+    key[i] = m;
+    idx[i] = (int32_t)i;
+}
+
+// Per-workgroup digit histograms, stored digit-major: hist[digit * nblk + block].
+__global__ __launch_bounds__(256) void radix_hist(const uint32_t *key, int64_t n, int shift, int32_t *hist,
+                                                  int64_t nblk)
+{
+    __shared__ int32_t h[NBUCKET];
+    h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SORT_BLK;
     for (int j = threadIdx.x; j < SORT_BLK; j += 256)
-        if (base + j < n) atomicAdd(&h[dist_bin(d[base + j], lo_bits, shift)], 1);
+        if (base + j < n) atomicAdd(&h[(key[base + j] >> shift) & (NBUCKET - 1)], 1);
     __syncthreads();
-    for (int b = threadIdx.x; b < NBIN; b += 256) hist[(int64_t)b * nblk + blockIdx.x] = h[b];
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of the bin-major histogram table by one workgroup (fixed order).
-__global__ __launch_bounds__(1024) void geo_scan(int32_t *hist, int64_t m)
+// Exclusive scan of the digit-major histogram table by one workgroup (fixed order).
+__global__ __launch_bounds__(1024) void radix_scan(int32_t *hist, int64_t m)
 {
     __shared__ int64_t part[1024];
     const int64_t per = (m + 1023) / 1024;
-    const int64_t b0 = threadIdx.x * per, b1 = min<int64_t>(m, b0 + per);
+    const int64_t b0 = min<int64_t>(m, threadIdx.x * per), b1 = min<int64_t>(m, b0 + per);
     int64_t s = 0;
     for (int64_t i = b0; i < b1; ++i) s += hist[i];
     part[threadIdx.x] = s;
@@ -126,29 +181,65 @@ __global__ __launch_bounds__(1024) void geo_scan(int32_t *hist, int64_t m)
     }
 }
 
-// Stable placement: positions assigned in index order inside each block (one lane walks the
-// block), then the copies run on all lanes. perm[pos] = original index.
-template <int DIM>
-__global__ __launch_bounds__(256) void geo_place(const double *d, const double *xv, int64_t n,
-                                                 uint64_t lo_bits, int shift, const int32_t *off,
-                                                 int64_t nblk, int32_t *perm, double *d_sorted,
-                                                 double *xv_sorted)
+// Stable scatter of one radix pass: positions are assigned in index order inside each block (one
+// lane walks the block), then all lanes move the (key, index) pairs.
+__global__ __launch_bounds__(256) void radix_place(const uint32_t *key_in, const int32_t *idx_in, int64_t n,
+                                                   int shift, const int32_t *off, int64_t nblk,
+                                                   uint32_t *key_out, int32_t *idx_out)
 {
-    __shared__ int32_t cur[NBIN];
+    __shared__ int32_t cur[NBUCKET];
     __shared__ int32_t pos[SORT_BLK];
     const int64_t base = (int64_t)blockIdx.x * SORT_BLK;
     const int cnt = (int)min<int64_t>(SORT_BLK, n - base);
-    for (int b = threadIdx.x; b < NBIN; b += 256) cur[b] = off[(int64_t)b * nblk + blockIdx.x];
+    cur[threadIdx.x] = off[(int64_t)threadIdx.x * nblk + blockIdx.x];
     __syncthreads();
     if (threadIdx.x == 0)
-        for (int j = 0; j < cnt; ++j) pos[j] = cur[dist_bin(d[base + j], lo_bits, shift)]++;
+        for (int j = 0; j < cnt; ++j) pos[j] = cur[(key_in[base + j] >> shift) & (NBUCKET - 1)]++;
     __syncthreads();
     for (int j = threadIdx.x; j < cnt; j += 256) {
-        const int64_t v = base + j, p = pos[j];
-        perm[p] = (int32_t)v;
-        d_sorted[p] = d[v];
+        key_out[pos[j]] = key_in[base + j];
+        idx_out[pos[j]] = idx_in[base + j];
+    }
+}
+
+// Smallest wall distance of each run of VBLOCK points in Z order.
+__global__ __launch_bounds__(256) void geo_blockmin(const double *d, const int32_t *idx, int64_t n, double *bmin)
+{
+    __shared__ double red[256];
+    const int64_t b0 = (int64_t)blockIdx.x * VBLOCK;
+    double m = HUGE_VAL;
+    for (int j = threadIdx.x; j < VBLOCK; j += 256)
+        if (b0 + j < n) m = fmin(m, d[idx[b0 + j]]);
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bmin[blockIdx.x] = red[0];
+}
+
+// Final layout: stored block r is Z-order block border[r]; slots past the end of the volume are
+// padding (perm -1, d = +inf, so psi = 0 and nothing is written for them).
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_gather(const int32_t *border, const int32_t *zidx, const double *d,
+                                                  const double *xv, int64_t n, int64_t n_pad, int32_t *perm,
+                                                  double *d_sorted, double *x_sorted)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n_pad) return;
+    const int64_t src = (int64_t)border[j / VBLOCK] * VBLOCK + j % VBLOCK;
+    if (src < n) {
+        const int32_t v = zidx[src];
+        perm[j] = v;
+        d_sorted[j] = d[v];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) xv_sorted[k * n + p] = xv[k * n + v];
+        for (int k = 0; k < DIM; ++k) x_sorted[k * n_pad + j] = xv[k * n + v];
+    } else {
+        perm[j] = -1;
+        d_sorted[j] = HUGE_VAL;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) x_sorted[k * n_pad + j] = 0.0;
     }
 }
 
@@ -158,18 +249,18 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
 {
     Pool *pool = ctx->pool.get();
     const int64_t n_s = g.n_s, n_v = g.n_v;
+    const int64_t nb = (n_v + VBLOCK - 1) / VBLOCK;
+    const int64_t n_pad = nb * VBLOCK;
+    g.n_pad = n_pad;
+    g.block_dmin.clear();
     RBF_TRY(g.xs.get(pool, sizeof(double) * DIM * n_s));
     RBF_HIP(hipMemcpyAsync(g.xs.ptr, xs, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
-    RBF_TRY(g.xv_sorted.get(pool, sizeof(double) * DIM * std::max<int64_t>(1, n_v)));
-    RBF_TRY(g.d_sorted.get(pool, sizeof(double) * std::max<int64_t>(1, n_v)));
-    RBF_TRY(g.perm.get(pool, sizeof(int32_t) * std::max<int64_t>(1, n_v)));
-    g.bytes = sizeof(double) * (DIM * (n_s + n_v) + n_v) + sizeof(int32_t) * n_v;
-    g.bin_off.assign(NBIN + 1, (int32_t)n_v);
-    g.bin_off[0] = 0;
-    g.lo_bits = 0;
-    g.shift = 0;
+    RBF_TRY(g.xv_sorted.get(pool, sizeof(double) * DIM * std::max<int64_t>(1, n_pad)));
+    RBF_TRY(g.d_sorted.get(pool, sizeof(double) * std::max<int64_t>(1, n_pad)));
+    RBF_TRY(g.perm.get(pool, sizeof(int32_t) * std::max<int64_t>(1, n_pad)));
+    g.bytes = sizeof(double) * (DIM * (n_s + n_pad) + n_pad) + sizeof(int32_t) * n_pad;
     if (n_v == 0) return RBF_OK;
-    DevBuf dtmp, mm, hist;
+    DevBuf dtmp, part, k0, k1, i0, i1, hist, bmin, border;
     const double *d = dwall;
     if (!d) {
         RBF_TRY(dtmp.get(pool, sizeof(double) * n_v));
@@ -178,44 +269,74 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
         RBF_HIP(hipGetLastError());
         d = dtmp.as<double>();
     }
-    RBF_TRY(mm.get(pool, 2 * sizeof(unsigned long long)));
-    unsigned long long init[2] = {~0ull, 0ull};
-    RBF_HIP(hipMemcpyAsync(mm.ptr, init, sizeof init, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(geo_minmax, dim3((unsigned)std::min<int64_t>((n_v + 255) / 256, 1024)), dim3(256), 0, s,
-                       d, n_v, mm.as<unsigned long long>());
-    unsigned long long mmh[2];
-    RBF_HIP(hipMemcpyAsync(mmh, mm.ptr, sizeof mmh, hipMemcpyDeviceToHost, s));
+    // Z-order keys over the volume's bounding box.
+    const int gb = (int)std::min<int64_t>((n_v + 255) / 256, 512);
+    RBF_TRY(part.get(pool, sizeof(double) * 2 * DIM * gb));
+    hipLaunchKernelGGL(geo_bbox<DIM>, dim3(gb), dim3(256), 0, s, xv, n_v, part.as<double>());
+    std::vector<double> ph((size_t)2 * DIM * gb);
+    RBF_HIP(hipMemcpyAsync(ph.data(), part.ptr, sizeof(double) * ph.size(), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
-    uint64_t lo = mmh[0] == ~0ull ? mmh[1] : mmh[0];
-    const uint64_t span = mmh[1] > lo ? mmh[1] - lo : 0;
-    int shift = 0;
-    while ((span >> shift) >= (uint64_t)NBIN) ++shift;
-    g.lo_bits = lo;
-    g.shift = shift;
+    Box box{};
+    for (int k = 0; k < DIM; ++k) {
+        double lo = HUGE_VAL, hi = -HUGE_VAL;
+        for (int b = 0; b < gb; ++b) {
+            lo = std::min(lo, ph[(size_t)b * 2 * DIM + k]);
+            hi = std::max(hi, ph[(size_t)b * 2 * DIM + DIM + k]);
+        }
+        if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(RBF_E_INVALID, "volume coordinates not finite");
+        box.lo[k] = lo;
+        box.scale[k] = hi > lo ? (DIM == 2 ? 65536.0 : 1024.0) / (hi - lo) : 0.0;
+    }
+    RBF_TRY(k0.get(pool, sizeof(uint32_t) * n_v));
+    RBF_TRY(k1.get(pool, sizeof(uint32_t) * n_v));
+    RBF_TRY(i0.get(pool, sizeof(int32_t) * n_v));
+    RBF_TRY(i1.get(pool, sizeof(int32_t) * n_v));
+    hipLaunchKernelGGL(geo_morton<DIM>, dim3((unsigned)((n_v + 255) / 256)), dim3(256), 0, s, xv, n_v, box,
+                       k0.as<uint32_t>(), i0.as<int32_t>());
+    // Stable LSD radix sort of (key, index), four 8-bit passes.
     const int64_t nblk = (n_v + SORT_BLK - 1) / SORT_BLK;
-    RBF_TRY(hist.get(pool, sizeof(int32_t) * NBIN * nblk));
-    hipLaunchKernelGGL(geo_hist, dim3((unsigned)nblk), dim3(256), 0, s, d, n_v, lo, shift, hist.as<int32_t>(), nblk);
-    hipLaunchKernelGGL(geo_scan, dim3(1), dim3(1024), 0, s, hist.as<int32_t>(), (int64_t)NBIN * nblk);
-    hipLaunchKernelGGL(geo_place<DIM>, dim3((unsigned)nblk), dim3(256), 0, s, d, xv, n_v, lo, shift,
-                       hist.as<const int32_t>(), nblk, g.perm.as<int32_t>(), g.d_sorted.as<double>(),
-                       g.xv_sorted.as<double>());
+    RBF_TRY(hist.get(pool, sizeof(int32_t) * NBUCKET * nblk));
+    DevBuf *kin = &k0, *kout = &k1, *iin = &i0, *iout = &i1;
+    for (int shift = 0; shift < 32; shift += 8) {
+        hipLaunchKernelGGL(radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, kin->as<const uint32_t>(), n_v, shift,
+                           hist.as<int32_t>(), nblk);
+        hipLaunchKernelGGL(radix_scan, dim3(1), dim3(1024), 0, s, hist.as<int32_t>(), (int64_t)NBUCKET * nblk);
+        hipLaunchKernelGGL(radix_place, dim3((unsigned)nblk), dim3(256), 0, s, kin->as<const uint32_t>(),
+                           iin->as<const int32_t>(), n_v, shift, hist.as<const int32_t>(), nblk,
+                           kout->as<uint32_t>(), iout->as<int32_t>());
+        std::swap(kin, kout);
+        std::swap(iin, iout);
+    }
     RBF_HIP(hipGetLastError());
-    // Bin starts (offset of block 0 of each bin) for the host-side prefix lookups.
-    std::vector<int32_t> starts(NBIN);
-    RBF_HIP(hipMemcpy2DAsync(starts.data(), sizeof(int32_t), hist.ptr, sizeof(int32_t) * nblk,
-                             sizeof(int32_t), NBIN, hipMemcpyDeviceToHost, s));
+    // Blocks of VBLOCK points in Z order, stored by increasing smallest wall distance: the
+    // points of any support distance D then lie in a prefix of whole blocks.
+    RBF_TRY(bmin.get(pool, sizeof(double) * nb));
+    hipLaunchKernelGGL(geo_blockmin, dim3((unsigned)nb), dim3(256), 0, s, d, iin->as<const int32_t>(), n_v,
+                       bmin.as<double>());
+    std::vector<double> bm(nb);
+    RBF_HIP(hipMemcpyAsync(bm.data(), bmin.ptr, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
-    for (int b = 0; b < NBIN; ++b) g.bin_off[b] = starts[b];
-    g.bin_off[NBIN] = (int32_t)n_v;
+    std::vector<int32_t> order(nb);
+    for (int64_t b = 0; b < nb; ++b) order[b] = (int32_t)b;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return bm[a] < bm[b]; });
+    g.block_dmin.resize(nb);
+    for (int64_t r = 0; r < nb; ++r) g.block_dmin[r] = bm[order[r]];
+    RBF_TRY(border.get(pool, sizeof(int32_t) * nb));
+    RBF_HIP(hipMemcpyAsync(border.ptr, order.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(geo_gather<DIM>, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, s,
+                       border.as<const int32_t>(), iin->as<const int32_t>(), d, xv, n_v, n_pad,
+                       g.perm.as<int32_t>(), g.d_sorted.as<double>(), g.xv_sorted.as<double>());
+    RBF_HIP(hipGetLastError());
+    RBF_HIP(hipStreamSynchronize(s));
     return RBF_OK;
 }
 
-// Reduced-volume prefix for support distance D: every point of every bin up to bin(D).
+// Reduced volume for support distance D: the stored blocks whose smallest wall distance is
+// below D (a prefix, in points).
 int64_t prefix_for(const Geometry &g, double D)
 {
-    if (g.n_v == 0) return 0;
-    const int b = dist_bin(D, g.lo_bits, g.shift);
-    return g.bin_off[std::min(NBIN, b + 1)];
+    const auto it = std::lower_bound(g.block_dmin.begin(), g.block_dmin.end(), D);
+    return (int64_t)(it - g.block_dmin.begin()) * VBLOCK;
 }
 
 uint64_t greedy_footprint(int dim, int64_t n_s, int64_t cap)
@@ -456,7 +577,8 @@ rbf_status Server::run(Req &q, hipStream_t s)
     pb.ld_ctrl = cs->capacity;
     pb.xc = cs->xc;
     pb.alpha = cs->alpha;
-    pb.n_p = g.n_v;
+    pb.n_p = g.n_pad;
+    pb.ld_out = g.n_v;
     pb.xp = g.xv_sorted.as<double>();
     pb.dwall = g.d_sorted.as<double>();
     pb.perm = g.perm.as<int32_t>();
@@ -591,7 +713,8 @@ rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, 
     pb.ld_ctrl = ld_ctrl;
     pb.xc = xc;
     pb.alpha = alpha;
-    pb.n_p = g->n_v;
+    pb.n_p = g->n_pad;
+    pb.ld_out = g->n_v;
     pb.xp = g->xv_sorted.as<double>();
     pb.dwall = g->d_sorted.as<double>();
     pb.perm = g->perm.as<int32_t>();

@@ -22,6 +22,7 @@ RBF_OK, RBF_W_CAP, RBF_W_BREAKDOWN = 0, 1, 2
 RBF_E_INVALID, RBF_E_NOMEM, RBF_E_NOT_SPD, RBF_E_DEVICE, RBF_E_NOT_FOUND, RBF_E_BUSY = -1, -2, -3, -4, -5, -6
 RBF_FP64, RBF_MIXED = 0, 1
 MAX_LEVELS = 8
+RBF_STOP_SKIPPED, RBF_STOP_EPS, RBF_STOP_CAP, RBF_STOP_ALL_SELECTED, RBF_STOP_BREAKDOWN = -1, 0, 1, 2, 3
 STOP_NAMES = {-1: "skipped", 0: "eps", 1: "cap", 2: "all_selected", 3: "breakdown"}
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
@@ -76,6 +77,7 @@ _SIGS = {
     "rbf_now": (_f64, []),
     "rbf_ctx_set_timing": (_i32, [_vp, _i32]),
     "rbf_ctx_kernel_time": (_i32, [_vp, ctypes.c_char_p, ctypes.POINTER(_f64), ctypes.POINTER(_i64)]),
+    "rbf_ctx_kernel_pairs": (_i32, [_vp, ctypes.c_char_p, ctypes.POINTER(_i64)]),
 }
 
 _lib = None
@@ -175,6 +177,14 @@ def rbf_now() -> float:
 
 def rbf_ctx_set_timing(ctx: int, enabled: bool) -> None:
     _check(lib().rbf_ctx_set_timing(ctx, 1 if enabled else 0), "rbf_ctx_set_timing")
+
+
+def rbf_ctx_kernel_pairs(ctx: int, kernel: str) -> int:
+    """(point, control) pairs a timed kernel evaluated since timing was enabled (culled pairs
+    excluded)."""
+    n = _i64()
+    _check(lib().rbf_ctx_kernel_pairs(ctx, kernel.encode(), ctypes.byref(n)), "rbf_ctx_kernel_pairs")
+    return n.value
 
 
 def rbf_ctx_kernel_time(ctx: int, kernel: str):

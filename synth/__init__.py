@@ -184,9 +184,10 @@ def oh_shell_3d(xyz: np.ndarray, n_chord: int, n_span: int, n_layers: int,
     return np.stack([X.reshape(-1), np.ascontiguousarray(Y).reshape(-1), Z.reshape(-1)])
 
 
-def min_hex_jacobian(vol: np.ndarray, surf: np.ndarray, n_chord: int, n_span: int, n_layers: int):
-    """Minimum corner Jacobian (scaled triple product) over the hexahedra of an O-H shell whose
-    layer 0 is the surface. Used as a mesh-validity post-check (positive means no inverted cell)."""
+def hex_jacobian_range(vol: np.ndarray, surf: np.ndarray, n_chord: int, n_span: int, n_layers: int):
+    """(min, max) of the corner Jacobian (triple product of the three edges at the first corner)
+    over the hexahedra of an O-H shell whose layer 0 is the surface. A valid mesh has every cell
+    of one sign, the sign of the undeformed mesh (a mesh-validity post-check)."""
     full = np.concatenate([surf.reshape(3, 1, n_span, n_chord),
                            vol.reshape(3, n_layers, n_span, n_chord)], axis=1)
     ip = np.roll(np.arange(n_chord), -1)
@@ -195,7 +196,20 @@ def min_hex_jacobian(vol: np.ndarray, surf: np.ndarray, n_chord: int, n_span: in
     ek = full[:, :-1, 1:, :] - a
     ej = full[:, 1:, :-1, :] - a
     jac = np.einsum("cljk,cljk->ljk", ej, np.cross(ei, ek, axis=0))
-    return float(jac.min()), float(np.abs(jac).max())
+    return float(jac.min()), float(jac.max())
+
+
+def hex_jacobians(vol: np.ndarray, surf: np.ndarray, n_chord: int, n_span: int, n_layers: int):
+    """Corner Jacobian of every hexahedron of the O-H shell, shape [n_layers, n_span - 1, n_chord]
+    (layer, span station, chord index)."""
+    full = np.concatenate([surf.reshape(3, 1, n_span, n_chord),
+                           vol.reshape(3, n_layers, n_span, n_chord)], axis=1)
+    ip = np.roll(np.arange(n_chord), -1)
+    a = full[:, :-1, :-1, :]
+    ei = full[:, :-1, :-1, ip] - a
+    ek = full[:, :-1, 1:, :] - a
+    ej = full[:, 1:, :-1, :] - a
+    return np.einsum("cljk,cljk->ljk", ej, np.cross(ei, ek, axis=0))
 
 
 # --------------------------------------------------------------------------------------------
@@ -218,6 +232,13 @@ class Workload:
     seeds: List[List[int]] = field(default_factory=lambda: [[0]])
     precision: str = "fp64"
     meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        # Row-contiguous SoA, as the device calls take them.
+        self.xs = np.ascontiguousarray(self.xs, dtype=np.float64)
+        self.ds = np.ascontiguousarray(self.ds, dtype=np.float64)
+        self.xv = np.ascontiguousarray(self.xv, dtype=np.float64)
+        self.dwall = np.ascontiguousarray(self.dwall, dtype=np.float64)
 
     @property
     def n_s(self) -> int:

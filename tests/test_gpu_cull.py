@@ -1,0 +1,103 @@
+"""Compact-support culling in the kernel sums (phi = 0 beyond R_l, eq. (2)) and the resident
+volume layout (Z-ordered blocks sorted by their smallest wall distance).
+
+Checks: the culled resident volume update equals the oracle within the FP64 bound, with exact
++0.0 wherever psi = 0, on ragged sizes (one partial block, fewer points than a block, sizes just
+around a block); it is bit for bit the plain volume update (other workgroups, other culling:
+dropped pairs are exact zeros and the kept ones keep their order); the evaluated-pair counter lies
+between the exact number of in-support pairs (brute force on the host) and the uncut count, and
+on a local support it is well below the uncut count (the culling takes effect).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from helpers import fp64_bound, sum_magnitude, to_dev
+from paper_2107_13887_amd import rbfdef
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(orc, seed, dim, n_s, n_v, radius, eps=1e-7):
+    w = synth.random_workload(seed, dim, n_s, n_v, radius, eps)
+    res = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds)
+    return w, res, np.ascontiguousarray(w.xs[:, res.ctrl_idx])
+
+
+def _in_support_pairs(w, res, xc, D):
+    """Exact count of (point, control) pairs with psi > 0 and ||x - x_c|| < R_l (brute force)."""
+    n = 0
+    for l in range(len(w.radius)):
+        a, b = res.level_off[l], res.level_off[l + 1]
+        pts = w.xv[:, w.dwall < D[l]]
+        if b == a or pts.shape[1] == 0:
+            continue
+        r2 = ((pts[:, :, None] - xc[:, None, a:b]) ** 2).sum(0)
+        n += int((r2 < (w.radius[l] * (1 - 1e-9)) ** 2).sum())
+    return n
+
+
+@pytest.mark.parametrize("dim,n_s,n_v,radius,D", [
+    (2, 400, 9001, [1.0, 0.15], [0.6, 0.6]),       # one partial block
+    (3, 500, 513, [1.2, 0.3], [0.8, 0.4]),          # a block and one point, per-level D
+    (3, 300, 511, [0.4], [2.0]),                    # fewer points than one block
+    (2, 350, 1536, [0.8, 0.2, 0.05], [0.5, 0.5, 0.5]),  # whole blocks, very local last level
+])
+def test_culled_resident_volume(gctx, orc, dim, n_s, n_v, radius, D):
+    w, res, xc = _case(orc, 300 + n_v, dim, n_s, n_v, radius)
+    print(f"case d{dim} n_s={n_s} n_v={n_v} R={radius} D={D} n_c={res.level_off[-1]}", flush=True)
+    ref = orc.volume(w.radius, D, res.level_off, xc, res.alpha, w.xv, w.dwall)
+    geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
+    dv = torch.full((dim, n_v), float("nan"), dtype=torch.float64, device="cuda:0")
+    rbfdef.rbf_ctx_set_timing(gctx, True)
+    rbfdef.rbf_geom_volume_update(gctx, geom, w.radius, D, list(res.level_off), to_dev(xc),
+                                  to_dev(res.alpha), dv)
+    torch.cuda.synchronize()
+    evaluated = rbfdef.rbf_ctx_kernel_pairs(gctx, "volume_ksum_fp64")
+    rbfdef.rbf_ctx_set_timing(gctx, False)
+    got = dv.cpu().numpy()
+    scale = np.sqrt((ref ** 2).sum(0)).max()
+    S = sum_magnitude(orc, w.radius, res.level_off, xc, res.alpha, w.xv, w.dwall, D)
+    err = np.sqrt(((got - ref) ** 2).sum(0)).max()
+    print(f"error {err:.3e} (bound {fp64_bound(scale, S):.3e})")
+    assert err <= fp64_bound(scale, S)
+    far = w.dwall >= max(D)
+    assert np.all(got[:, far] == 0.0) and not np.any(np.signbit(got[:, far]))
+    # evaluated pairs: at least every in-support pair, at most every pair of every stored block
+    need = _in_support_pairs(w, res, xc, D)
+    n_pad = -(-n_v // 512) * 512
+    upper = sum(n_pad * (res.level_off[l + 1] - res.level_off[l]) for l in range(len(radius)))
+    print(f"pairs: in support {need}, evaluated {evaluated}, uncut upper bound {upper}")
+    assert need <= evaluated <= upper
+    # the plain call (caller's order, per-call compaction) gives the same bits
+    plain = rbfdef.rbf_volume_update(gctx, w.radius, D, list(res.level_off), to_dev(xc), to_dev(res.alpha),
+                                     to_dev(w.xv), to_dev(w.dwall))
+    torch.cuda.synchronize()
+    assert torch.equal(plain, dv)
+    rbfdef.rbf_geom_release(gctx, geom)
+
+
+def test_culling_takes_effect(gctx, orc):
+    """A local support: the resident layout evaluates well under half of the uncut pairs."""
+    w, res, xc = _case(orc, 411, 2, 600, 40000, [0.08], eps=1e-6)
+    D = [3.0]
+    geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
+    dv = torch.empty((2, w.n_v), dtype=torch.float64, device="cuda:0")
+    rbfdef.rbf_ctx_set_timing(gctx, True)
+    rbfdef.rbf_geom_volume_update(gctx, geom, w.radius, D, list(res.level_off), to_dev(xc),
+                                  to_dev(res.alpha), dv)
+    torch.cuda.synchronize()
+    evaluated = rbfdef.rbf_ctx_kernel_pairs(gctx, "volume_ksum_fp64")
+    rbfdef.rbf_ctx_set_timing(gctx, False)
+    need = _in_support_pairs(w, res, xc, D)
+    n_d = int((w.dwall < D[0]).sum())
+    total = n_d * res.level_off[1]
+    print(f"in support {need} ({need / total:.3f}), evaluated {evaluated} ({evaluated / total:.3f}) of {total}")
+    assert need <= evaluated < 0.5 * total
+    ref = orc.volume(w.radius, D, res.level_off, xc, res.alpha, w.xv, w.dwall)
+    scale = np.sqrt((ref ** 2).sum(0)).max()
+    S = sum_magnitude(orc, w.radius, res.level_off, xc, res.alpha, w.xv, w.dwall, D)
+    err = np.sqrt(((dv.cpu().numpy() - ref) ** 2).sum(0)).max()
+    assert err <= fp64_bound(scale, S)
+    rbfdef.rbf_geom_release(gctx, geom)
