@@ -116,6 +116,10 @@ typedef struct {
     int32_t level_off[RBF_MAX_LEVELS + 1]; /* out */
     int32_t level_stop[RBF_MAX_LEVELS];    /* out: RBF_STOP_* per level */
     double level_max_err[RBF_MAX_LEVELS];  /* out: max_i ||E_i|| (FP64) at each level close */
+    double level_in_max[RBF_MAX_LEVELS];   /* out: max_i ||dS_l,i|| of each level's input, the
+                                              (dS_l)^max of the support distance D_l = k (dS_l)^max
+                                              (section 4); 0 for levels not run */
+    double level_seconds[RBF_MAX_LEVELS];  /* out: host wall time of each level (timing only) */
     int64_t n_iterations;                  /* out: argmax selections made (seeds excluded) */
 } rbf_ctrl_set;
 
@@ -183,7 +187,9 @@ typedef struct {
     rbf_geom geom;
     const double *ds;          /* device [dim][n_s], caller-owned until the request is DONE */
     rbf_greedy_params params;  /* copied at submit (seed arrays included) */
-    double D[RBF_MAX_LEVELS];  /* wall-distance support per level */
+    double D[RBF_MAX_LEVELS];  /* wall-distance support per level (used when d_factor == 0) */
+    double d_factor;           /* k > 0: D_l = k max_i ||dS_l,i|| per level after the greedy
+                                  (section 4, volume reduction factor; the paper uses k = 5) */
     int32_t warm_start;        /* 1: seed each level with this geometry's previous control set */
     double *dv;                /* device [dim][n_v] output in the geometry's original order */
     rbf_ctrl_set *out;         /* NULL, or caller-owned until DONE (device arrays as above) */

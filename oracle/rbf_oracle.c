@@ -8,7 +8,7 @@
  * calls it.
  *
  * Everything is FP64 and written as plain loops that follow the paper's statement of the method:
- *   - Wendland C2 basis, eq. (2) and Table 1;
+ *   - Wendland basis functions of Table 1 (C2, eq. (2), by default; C0, C4, C6 selectable);
  *   - interpolation weights from Phi_cc alpha = dS_c, eq. (9) restricted to the control set;
  *   - greedy error E = dS - Phi_sc alpha, eq. (12), and argmax selection (Section 3);
  *   - multi-level residual dS_{l+1} = E (Section 3, the multi-level subspace scheme);
@@ -61,6 +61,42 @@ double orc_wendland_c2(double eta)
 #endif
 }
 
+/* The Wendland functions of Table 1, selected by `basis`, each zero from eta = 1 on:
+ *   C0: (1 - eta)^2
+ *   C2: (1 - eta)^4 (4 eta + 1)                       (the paper's choice, eq. (2))
+ *   C4: (1 - eta)^6 (35/3 eta^2 + 6 eta + 1)
+ *   C6: (1 - eta)^8 (32 eta^3 + 25 eta^2 + 8 eta + 1)
+ * Unknown codes give NaN. */
+#define ORC_C2 0
+#define ORC_C0 1
+#define ORC_C4 2
+#define ORC_C6 3
+double orc_wendland(int basis, double eta)
+{
+    if (basis == ORC_C2) return orc_wendland_c2(eta);
+    if (eta >= 1.0) return 0.0;
+    double t = 1.0 - eta;
+    if (basis == ORC_C0) return t * t;
+#ifdef ORC_MUTANT_C4_COEF
+    if (basis == ORC_C4) return t * t * t * t * t * t * (35.0 / 3.0 * eta * eta + 5.0 * eta + 1.0);
+#else
+    if (basis == ORC_C4) return t * t * t * t * t * t * (35.0 / 3.0 * eta * eta + 6.0 * eta + 1.0);
+#endif
+#ifdef ORC_MUTANT_C6_POWER
+    if (basis == ORC_C6)
+        return t * t * t * t * t * t * t * (32.0 * eta * eta * eta + 25.0 * eta * eta + 8.0 * eta + 1.0);
+#else
+    if (basis == ORC_C6)
+        return t * t * t * t * t * t * t * t * (32.0 * eta * eta * eta + 25.0 * eta * eta + 8.0 * eta + 1.0);
+#endif
+    return NAN;
+}
+
+static int basis_ok(int basis)
+{
+    return basis == ORC_C0 || basis == ORC_C2 || basis == ORC_C4 || basis == ORC_C6;
+}
+
 /* Wall-distance function of Section 4: psi(xi) = 1 - xi for 0 <= xi < 1, 0 otherwise. */
 double orc_psi(double xi)
 {
@@ -89,13 +125,13 @@ static double dist(int dim, const double *a, int64_t lda, int64_t ia,
 /*   f_k(p) = sum_c alpha_k,c phi(||p - x_c|| / R),   summed in control order.              */
 /* ---------------------------------------------------------------------------------------- */
 void orc_eval(int dim, double radius, int64_t n_c, const double *xc, const double *alpha,
-              int64_t n_p, const double *xp, double *out)
+              int64_t n_p, const double *xp, double *out, int basis)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n_p; ++i) {
         double acc[3] = {0.0, 0.0, 0.0};
         for (int64_t c = 0; c < n_c; ++c) {
-            double phi = orc_wendland_c2(dist(dim, xp, n_p, i, xc, n_c, c) / radius);
+            double phi = orc_wendland(basis, dist(dim, xp, n_p, i, xc, n_c, c) / radius);
             for (int k = 0; k < dim; ++k) acc[k] += phi * alpha[k * n_c + c];
         }
         for (int k = 0; k < dim; ++k) out[k * n_p + i] = acc[k];
@@ -106,14 +142,14 @@ void orc_eval(int dim, double radius, int64_t n_c, const double *xc, const doubl
 /* Dense weight solve, eq. (9) on a given point set: Phi alpha = ds by textbook Cholesky.     */
 /* ---------------------------------------------------------------------------------------- */
 int orc_solve_weights(int dim, double radius, int64_t n_c, const double *xc, const double *dsc,
-                      double *alpha)
+                      double *alpha, int basis)
 {
-    if (dim < 2 || dim > 3 || n_c <= 0 || !(radius > 0.0)) return ORC_E_INVALID;
+    if (dim < 2 || dim > 3 || n_c <= 0 || !(radius > 0.0) || !basis_ok(basis)) return ORC_E_INVALID;
     double *L = (double *)calloc((size_t)n_c * (size_t)n_c, sizeof(double));
     if (!L) return ORC_E_NOMEM;
     for (int64_t i = 0; i < n_c; ++i)
         for (int64_t j = 0; j <= i; ++j)
-            L[i * n_c + j] = orc_wendland_c2(dist(dim, xc, n_c, i, xc, n_c, j) / radius);
+            L[i * n_c + j] = orc_wendland(basis, dist(dim, xc, n_c, i, xc, n_c, j) / radius);
     /* Cholesky-Banachiewicz: L L^T = Phi. */
     for (int64_t i = 0; i < n_c; ++i) {
         for (int64_t j = 0; j <= i; ++j) {
@@ -160,12 +196,12 @@ typedef struct {
 /* Border the factor with the control point p: l = L^-1 phi(X_C, x_p), d^2 = phi(0) - l.l.
  * Returns 0 on success, 1 when the new pivot is not positive (breakdown). */
 static int chol_append(packed_chol *f, int dim, const double *xs, int64_t n_s, double radius,
-                       const int64_t *ctrl, int64_t p)
+                       const int64_t *ctrl, int64_t p, int basis)
 {
     int64_t n = f->n;
     double *row = ROW(f, n);
     for (int64_t j = 0; j < n; ++j)
-        row[j] = orc_wendland_c2(dist(dim, xs, n_s, ctrl[j], xs, n_s, p) / radius);
+        row[j] = orc_wendland(basis, dist(dim, xs, n_s, ctrl[j], xs, n_s, p) / radius);
     double ll = 0.0;
     for (int64_t i = 0; i < n; ++i) {                 /* forward substitution */
         double s = row[i];
@@ -174,7 +210,7 @@ static int chol_append(packed_chol *f, int dim, const double *xs, int64_t n_s, d
         row[i] = s / ri[i];
         ll += row[i] * row[i];
     }
-    double d2 = orc_wendland_c2(0.0) - ll;
+    double d2 = orc_wendland(basis, 0.0) - ll;
     /* l.l carries about (n + 1) ulps of rounding: a pivot below that is numerically zero. */
     if (!(d2 > (double)(n + 1) * DBL_EPSILON)) return 1;
     row[n] = sqrt(d2);
@@ -211,13 +247,13 @@ static void chol_solve(const packed_chol *f, int dim, const double *r, int64_t n
 /* E = r - Phi_sC alpha at every surface point, eq. (12), control sums in selection order. */
 static void surface_error(int dim, const double *xs, int64_t n_s, const double *r, double radius,
                           const int64_t *ctrl, int64_t n, const double *alpha, int64_t lda,
-                          double *E)
+                          double *E, int basis)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n_s; ++i) {
         double acc[3] = {0.0, 0.0, 0.0};
         for (int64_t c = 0; c < n; ++c) {
-            double phi = orc_wendland_c2(dist(dim, xs, n_s, i, xs, n_s, ctrl[c]) / radius);
+            double phi = orc_wendland(basis, dist(dim, xs, n_s, i, xs, n_s, ctrl[c]) / radius);
             for (int k = 0; k < dim; ++k) acc[k] += phi * alpha[k * lda + c];
         }
         for (int k = 0; k < dim; ++k) {
@@ -253,10 +289,11 @@ int orc_greedy(int dim, int64_t n_s, const double *xs, const double *ds,
                int n_levels, const double *radius, double eps, double rho, int64_t cap,
                const int64_t *seed_idx, const int32_t *seed_off,
                int64_t *ctrl_idx, double *alpha, int32_t *level_off, double *level_max_err,
-               int32_t *level_stop, int32_t *n_levels_used, double *e_final, double *history)
+               int32_t *level_stop, int32_t *n_levels_used, double *e_final, double *history,
+               int basis)
 {
     if (dim < 2 || dim > 3 || n_s <= 0 || n_levels < 1 || n_levels > 8 || cap <= 0 ||
-        !(eps >= 0.0) || !(rho > 0.0 && rho <= 1.0))
+        !(eps >= 0.0) || !(rho > 0.0 && rho <= 1.0) || !basis_ok(basis))
         return ORC_E_INVALID;
     for (int l = 0; l < n_levels; ++l)
         if (!(radius[l] > 0.0)) return ORC_E_INVALID;
@@ -300,7 +337,7 @@ int orc_greedy(int dim, int64_t n_s, const double *xs, const double *ds,
         for (int32_t s = seed_off[l]; s < seed_off[l + 1]; ++s) {
             int64_t p = seed_idx[s];
             if (total + n >= cap) { stop = ORC_STOP_CAP; break; }
-            if (chol_append(&f, dim, xs, n_s, radius[l], C, p)) { stop = ORC_STOP_BREAKDOWN; break; }
+            if (chol_append(&f, dim, xs, n_s, radius[l], C, p, basis)) { stop = ORC_STOP_BREAKDOWN; break; }
             C[n++] = p;
             sel[p] = 1;
         }
@@ -308,7 +345,7 @@ int orc_greedy(int dim, int64_t n_s, const double *xs, const double *ds,
         for (;;) {
             /* alpha from Phi_cc alpha = r_C (eq. (9) on the control set), then E (eq. (12)). */
             chol_solve(&f, dim, r, n_s, C, alv, nmax + 1, tmp);
-            surface_error(dim, xs, n_s, r, radius[l], C, n, alv, nmax + 1, E);
+            surface_error(dim, xs, n_s, r, radius[l], C, n, alv, nmax + 1, E, basis);
             if (stop >= 0) break;
             /* Largest error signal among the points not yet selected in this level. */
             int64_t p = -1;
@@ -325,7 +362,7 @@ int orc_greedy(int dim, int64_t n_s, const double *xs, const double *ds,
             if (p < 0) { stop = ORC_STOP_ALL_SELECTED; break; }
             if (m2 < target2) { stop = ORC_STOP_EPS; break; }
             if (total + n >= cap) { stop = ORC_STOP_CAP; break; }
-            if (chol_append(&f, dim, xs, n_s, radius[l], C, p)) { stop = ORC_STOP_BREAKDOWN; break; }
+            if (chol_append(&f, dim, xs, n_s, radius[l], C, p, basis)) { stop = ORC_STOP_BREAKDOWN; break; }
             if (history) history[n_hist] = sqrt(m2);
             ++n_hist;
             C[n++] = p;
@@ -368,7 +405,7 @@ int orc_greedy(int dim, int64_t n_s, const double *xs, const double *ds,
 /* ---------------------------------------------------------------------------------------- */
 void orc_volume(int dim, int n_levels, const double *radius, const double *D,
                 const int32_t *level_off, int64_t ld_ctrl, const double *xc, const double *alpha,
-                int64_t n_v, const double *xv, const double *dwall, double *dv)
+                int64_t n_v, const double *xv, const double *dwall, double *dv, int basis)
 {
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t v = 0; v < n_v; ++v) {
@@ -381,7 +418,7 @@ void orc_volume(int dim, int n_levels, const double *radius, const double *D,
             if (w == 0.0) continue;
             double acc[3] = {0.0, 0.0, 0.0};
             for (int64_t c = level_off[l]; c < level_off[l + 1]; ++c) {
-                double phi = orc_wendland_c2(dist(dim, xv, n_v, v, xc, ld_ctrl, c) / radius[l]);
+                double phi = orc_wendland(basis, dist(dim, xv, n_v, v, xc, ld_ctrl, c) / radius[l]);
                 for (int k = 0; k < dim; ++k) acc[k] += phi * alpha[k * ld_ctrl + c];
             }
             for (int k = 0; k < dim; ++k) out[k] += w * acc[k];

@@ -801,8 +801,11 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     for (int l = 0; l < RBF_MAX_LEVELS; ++l) {
         out->level_stop[l] = RBF_STOP_SKIPPED;
         out->level_max_err[l] = 0.0;
+        out->level_in_max[l] = 0.0;
+        out->level_seconds[l] = 0.0;
     }
     for (int l = 0; l < prm.n_levels; ++l) {
+        const double t_level = now_seconds();
         const double Rl = prm.radius[l];
         a.R = Rl;
         a.cap_level = std::min<int64_t>(cols, cap - total);
@@ -893,6 +896,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         }
         const int64_t n = hs.n;
         out->level_stop[l] = hs.stop;
+        out->level_in_max[l] = std::sqrt(hs.rmax2);   // max ||dS_l|| (set at level start)
         // Weights: L^T alpha = y, blocked from the bottom.
         double *alpha = out->alpha + total;
         if (n > 0) {
@@ -956,6 +960,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         RBF_HIP(hipMemcpyAsync(&hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
         RBF_HIP(hipStreamSynchronize(s));
         out->level_max_err[l] = std::sqrt(hs.rmax2);
+        out->level_seconds[l] = now_seconds() - t_level;
         if (std::sqrt(hs.rmax2) < prm.eps_abs || out->level_stop[l] == RBF_STOP_CAP) break;
     }
     for (int l = used; l < prm.n_levels; ++l) out->level_off[l + 1] = (int32_t)total;

@@ -565,14 +565,18 @@ rbf_status Server::run(Req &q, hipStream_t s)
     std::vector<LevelCache> fresh;
     rbf_status st = run_greedy(ctx_, p, g.n_s, g.xs.as<double>(), q.r.ds, cs, s, &g.levels, &fresh);
     if (st < 0) return st;
-    // Volume update on the resident, wall-distance-ordered volume.
+    // Volume update on the resident geometry. Support distances: the request's D_l, or
+    // D_l = k max ||dS_l|| from the greedy (section 4). Levels without controls add nothing and
+    // are left out.
     SumProblem pb;
     pb.dim = dim;
-    pb.n_levels = p.n_levels;
+    pb.n_levels = 0;
     double dmax = 0.0;
     for (int l = 0; l < p.n_levels; ++l) {
-        pb.lv[l] = SumLevel{1.0 / p.radius[l], q.r.D[l], cs->level_off[l], cs->level_off[l + 1]};
-        dmax = std::max(dmax, q.r.D[l]);
+        const double Dl = q.r.d_factor > 0.0 ? q.r.d_factor * cs->level_in_max[l] : q.r.D[l];
+        if (cs->level_off[l + 1] == cs->level_off[l] || !(Dl > 0.0)) continue;
+        pb.lv[pb.n_levels++] = SumLevel{1.0 / p.radius[l], Dl, cs->level_off[l], cs->level_off[l + 1]};
+        dmax = std::max(dmax, Dl);
     }
     pb.ld_ctrl = cs->capacity;
     pb.xc = cs->xc;
@@ -752,8 +756,11 @@ rbf_status rbf_submit(rbf_ctx ctx, const rbf_request *req, rbf_ticket *out)
     RBF_TRY(validate_params(p, g->n_s));
     if (p.dim != g->dim) return fail(RBF_E_INVALID, "request dim %d != geometry dim %d", p.dim, g->dim);
     if (!req->ds || (g->n_v > 0 && !req->dv)) return fail(RBF_E_INVALID, "NULL device array");
-    for (int l = 0; l < p.n_levels; ++l)
-        if (!(req->D[l] > 0.0) || !std::isfinite(req->D[l])) return fail(RBF_E_INVALID, "D[%d] must be > 0", l);
+    if (!(req->d_factor >= 0.0) || !std::isfinite(req->d_factor))
+        return fail(RBF_E_INVALID, "d_factor must be finite and >= 0");
+    if (req->d_factor == 0.0)
+        for (int l = 0; l < p.n_levels; ++l)
+            if (!(req->D[l] > 0.0) || !std::isfinite(req->D[l])) return fail(RBF_E_INVALID, "D[%d] must be > 0", l);
     if (req->out && (!req->out->ctrl_idx || !req->out->xc || !req->out->alpha ||
                      req->out->capacity < p.max_ctrl_total))
         return fail(RBF_E_INVALID, "out control set arrays missing or too small");

@@ -41,12 +41,13 @@ class rbf_ctrl_set(ctypes.Structure):
     _fields_ = [("capacity", _i64), ("ctrl_idx", _vp), ("xc", _vp), ("alpha", _vp),
                 ("e_final", _vp), ("n_levels_used", _i32), ("stop_reason", _i32),
                 ("level_off", _i32 * (MAX_LEVELS + 1)), ("level_stop", _i32 * MAX_LEVELS),
-                ("level_max_err", _f64 * MAX_LEVELS), ("n_iterations", _i64)]
+                ("level_max_err", _f64 * MAX_LEVELS), ("level_in_max", _f64 * MAX_LEVELS),
+                ("level_seconds", _f64 * MAX_LEVELS), ("n_iterations", _i64)]
 
 
 class rbf_request(ctypes.Structure):
     _fields_ = [("geom", _vp), ("ds", _vp), ("params", rbf_greedy_params),
-                ("D", _f64 * MAX_LEVELS), ("warm_start", _i32), ("dv", _vp),
+                ("D", _f64 * MAX_LEVELS), ("d_factor", _f64), ("warm_start", _i32), ("dv", _vp),
                 ("out", ctypes.POINTER(rbf_ctrl_set))]
 
 
@@ -211,10 +212,16 @@ class CtrlSet:
     n_levels_used: int
     n_iterations: int
     status: int
+    level_in_max: List[float] = field(default_factory=list)    # max ||dS_l|| per level input
+    level_seconds: List[float] = field(default_factory=list)
 
     @property
     def total(self) -> int:
         return self.level_off[-1]
+
+    def support_distances(self, k: float) -> List[float]:
+        """D_l = k max_i ||dS_l,i|| for the levels run (section 4, volume reduction factor k)."""
+        return [k * self.level_in_max[l] for l in range(self.n_levels_used)]
 
     def level(self, l: int):
         a, b = self.level_off[l], self.level_off[l + 1]
@@ -277,7 +284,9 @@ def rbf_greedy_select(ctx: int, xs, ds, radius: Sequence[float], eps: float, rho
                    e_final=ef, level_off=[out.level_off[l] for l in range(len(radius) + 1)],
                    level_stop=[out.level_stop[l] for l in range(len(radius))],
                    level_max_err=[out.level_max_err[l] for l in range(len(radius))],
-                   n_levels_used=nl, n_iterations=out.n_iterations, status=st)
+                   n_levels_used=nl, n_iterations=out.n_iterations, status=st,
+                   level_in_max=[out.level_in_max[l] for l in range(len(radius))],
+                   level_seconds=[out.level_seconds[l] for l in range(len(radius))])
 
 
 def rbf_solve_weights(ctx: int, radius: float, xc, dsc, alpha=None, stream=None):
@@ -399,7 +408,7 @@ class Request:
 
 def rbf_submit(ctx: int, geom: int, ds, dv, radius: Sequence[float], eps: float, D: Sequence[float],
                rho: float = 0.1, cap: int = 0, seeds=None, precision: str = "mixed",
-               warm_start: bool = False, want_ctrl: bool = False) -> Request:
+               warm_start: bool = False, want_ctrl: bool = False, d_factor: float = 0.0) -> Request:
     import torch
 
     dim, n_s = ds.shape
@@ -412,6 +421,7 @@ def rbf_submit(ctx: int, geom: int, ds, dv, radius: Sequence[float], eps: float,
     D = list(D) if len(D) == nl else [float(D[0])] * nl
     for l in range(nl):
         req.D[l] = float(D[l])
+    req.d_factor = float(d_factor)
     req.warm_start = 1 if warm_start else 0
     req.dv, _ = _dev(dv, "dv", dim, None)
     cs = None
@@ -444,6 +454,8 @@ def _fill_ctrl(r: Request):
     r.out.level_max_err = [oc.level_max_err[l] for l in range(nl)]
     r.out.n_levels_used = oc.n_levels_used
     r.out.n_iterations = oc.n_iterations
+    r.out.level_in_max = [oc.level_in_max[l] for l in range(nl)]
+    r.out.level_seconds = [oc.level_seconds[l] for l in range(nl)]
 
 
 def rbf_poll(ctx: int, r: Request) -> rbf_req_info:

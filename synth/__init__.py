@@ -232,6 +232,7 @@ class Workload:
     seeds: List[List[int]] = field(default_factory=lambda: [[0]])
     precision: str = "fp64"
     meta: dict = field(default_factory=dict)
+    d_factor: float = 0.0     # k > 0: support distances D_l = k max ||dS_l|| (section 4)
 
     def __post_init__(self):
         # Row-contiguous SoA, as the device calls take them.
@@ -369,6 +370,32 @@ def workload_cfg3(n_chord: int = 400, n_span: int = 200, n_layers: int = 50, cap
                     radius=[3.0, 0.8, 0.2], eps=1e-4, D=1.0, seeds=[[0]], cap=cap,
                     precision="mixed",
                     meta=dict(cfg=3, n_chord=n_chord, n_span=n_span, n_layers=n_layers))
+
+
+def workload_sine2d(n_s: int = 4000, n_layers: int = 100) -> Workload:
+    """The paper's global-deformation benchmark in 2D (Results, airfoil): every surface point of
+    the NACA0012 moves by dy = 0.01 sin(15 pi x), x along the chord in units of c. The paper's
+    parameters: Wendland C2 with R = 2c on all five levels, a reduction of 0.1 per level (so
+    eps = 1e-5 of max ||dS||), volume reduction factor k = 5. Mesh as the multi-level ice case."""
+    first = 2.5e-4 if n_s >= 4000 else 1e-3
+    xs, xv = airfoil_2d(n_s, n_layers, first)
+    ds = np.stack([np.zeros(n_s), 0.01 * np.sin(15.0 * np.pi * xs[0])])
+    top = float(np.sqrt((ds ** 2).sum(axis=0)).max())
+    return Workload("sine2d_naca0012", 2, xs, ds, xv, wall_distance(xs, xv), radius=[2.0] * 5,
+                    eps=1e-5 * top, D=1.0, seeds=[[0]], cap=0, d_factor=5.0,
+                    meta=dict(n_layers=n_layers))
+
+
+def workload_sine3d(n_chord: int = 400, n_span: int = 200, n_layers: int = 50, cap: int = 4000) -> Workload:
+    """The paper's global-deformation benchmark on the swept wing (eq. (27)): the displacement
+    normal to the wing plane is 0.03 sin(4 pi s) with s the spanwise coordinate in units of c (the
+    paper's y and z are this generator's z and y). R = 3c on four levels, reduction 0.1 per level,
+    eps = 1e-4c, at most ``cap`` control points, k = 5. Mesh as the iced-wing case."""
+    xyz, vol, xc, zc, yk = wing_3d(n_chord, n_span, n_layers)
+    ds = np.stack([np.zeros(xyz.shape[1]), np.zeros(xyz.shape[1]), 0.03 * np.sin(4.0 * np.pi * xyz[1])])
+    return Workload("sine3d_swept_wing", 3, xyz, ds, vol, wall_distance(xyz, vol), radius=[3.0] * 4,
+                    eps=1e-4, D=1.0, seeds=[[0]], cap=cap, d_factor=5.0,
+                    meta=dict(n_chord=n_chord, n_span=n_span, n_layers=n_layers))
 
 
 def workload(cfg: int, **kw) -> Workload:

@@ -20,8 +20,9 @@ def pairwise_distance(a, b):
     return np.sqrt((diff**2).sum(axis=0))
 
 
-def greedy_bruteforce(xs, ds, radius, eps, rho=0.1, cap=0, seeds=None):
-    """Returns (per-level control lists, per-level alpha [dim, n_l], final residual)."""
+def greedy_bruteforce(xs, ds, radius, eps, rho=0.1, cap=0, seeds=None, phi=phi_expanded):
+    """Returns (per-level control lists, per-level alpha [dim, n_l], final residual). ``phi`` is
+    the basis as a vectorised function of eta (Wendland C2 by default)."""
     xs = np.asarray(xs, dtype=np.float64)
     r = np.array(ds, dtype=np.float64)
     n = xs.shape[1]
@@ -32,7 +33,7 @@ def greedy_bruteforce(xs, ds, radius, eps, rho=0.1, cap=0, seeds=None):
     total = 0
     for l, R in enumerate(radius):
         last = l == len(radius) - 1
-        Phi = phi_expanded(dist / R)
+        Phi = phi(dist / R)
         rmax = np.sqrt((r**2).sum(axis=0)).max()
         target = eps if last else max(eps, rho * rmax)
         C = []

@@ -38,6 +38,88 @@ def pin_wendland_c2_cutoff(o):
         assert o.wendland_c2(1.0 - h) == h**4 * (5.0 - 4.0 * h), h
 
 
+_TABLE1 = {"c0": (2, 0), "c2": (4, 1), "c4": (6, 2), "c6": (8, 3)}   # (power of 1 - eta, k)
+
+
+def pin_wendland_table1_values(o):
+    """Table 1 at points where the value is exact in binary (C0, C2, C6; C4 has the constant
+    35/3 and is checked to a few ulps): phi(0) = 1 for every function, 0 from eta = 1 on."""
+    exact = {"c0": {0.5: 0.25, 0.25: 9.0 / 16.0, 0.75: 1.0 / 16.0},
+             "c2": {0.5: 3.0 / 16.0, 0.25: 81.0 / 128.0},
+             "c6": {0.5: 61.0 / 1024.0, 0.25: 531441.0 / 1048576.0}}
+    for b in _TABLE1:
+        assert o.wendland(b, 0.0) == 1.0, b
+        for eta in (1.0, 1.25, 9.0):
+            assert o.wendland(b, eta) == 0.0, (b, eta)
+        for eta, val in exact.get(b, {}).items():
+            assert o.wendland(b, eta) == val, (b, eta)
+    for eta, val in {0.5: 83.0 / 768.0, 0.25: 112995.0 / 196608.0}.items():
+        assert abs(o.wendland("c4", eta) - val) <= 4e-16 * val, eta
+    for eta in np.linspace(0.0, 0.99, 37):
+        assert o.wendland("c2", eta) == o.wendland_c2(eta)
+
+
+def pin_wendland_table1_smoothness(o):
+    """Wendland's construction: the function with (1 - eta)^m as a factor has m - 1 vanishing
+    derivatives at eta = 1, and the one of smoothness C^2k has vanishing odd derivatives of
+    order < 2k at eta = 0 (it is an even, 2k-times differentiable function of r there). Checked
+    on the polynomial through samples of the oracle (exact interpolation, degree m + k)."""
+    from numpy.polynomial import polynomial as P
+
+    for b, (m, k) in _TABLE1.items():
+        deg = m + k
+        nodes = 0.5 - 0.5 * np.cos(np.pi * (np.arange(deg + 1) + 0.5) / (deg + 1))
+        vals = np.array([o.wendland(b, e) for e in nodes])
+        coef = np.linalg.solve(np.vander(nodes, deg + 1, increasing=True), vals)
+        for j in range(m):
+            dj = P.polyval(1.0, P.polyder(coef, j)) if j else P.polyval(1.0, coef)
+            # rounding scale of the j-th derivative at 1: sum_i |c_i| i! / (i - j)!
+            scale = sum(abs(c) * math.factorial(i) / math.factorial(i - j) for i, c in enumerate(coef) if i >= j)
+            assert abs(dj) <= 1e-9 * scale, (b, "eta=1", j, dj, scale)
+        for j in range(1, 2 * k, 2):
+            # phi^(j)(0) = j! c_j, zero up to the fit's rounding (relative to the largest c_i)
+            assert abs(coef[j]) <= 1e-10 * np.abs(coef).max(), (b, "eta=0", j, coef[j])
+        if k == 0:
+            assert abs(P.polyval(0.0, P.polyder(coef, 1)) + 2.0) <= 1e-9   # C0: slope -2 at 0
+    # the test itself detects a wrong coefficient: 6 eta -> 5 eta in C4 breaks phi'(0) = 0
+    bad = lambda e: (1 - e) ** 6 * (35.0 / 3.0 * e * e + 5.0 * e + 1.0)
+    assert abs((bad(1e-6) - bad(0.0)) / 1e-6) > 0.5
+
+
+def pin_wendland_table1_positive_definite(o):
+    """Every function of Table 1 is positive definite on R^3 (Wendland 1995): the matrix on
+    random 3D points has positive eigenvalues, and the oracle's weight solve with that basis
+    equals LAPACK's."""
+    rng = np.random.default_rng(21)
+    xc = rng.uniform(-1, 1, (3, 70))
+    dsc = rng.uniform(-0.05, 0.05, (3, 70))
+    dist = pairwise_distance(xc, xc) / 1.3
+    for b in _TABLE1:
+        Phi = np.vectorize(lambda e: o.wendland(b, e))(dist)
+        assert np.linalg.eigvalsh(Phi).min() > 0.0, b
+        st, alpha = o.solve_weights(1.3, xc, dsc, basis=b)
+        assert st == 0, b
+        ref = np.linalg.solve(Phi, dsc.T).T
+        assert np.abs(alpha - ref).max() <= 1e-9 * np.abs(ref).max(), b
+
+
+def pin_greedy_bruteforce_table1(o):
+    """The greedy with the C0, C4 and C6 bases gives the brute-force selection sequence (fresh
+    dense solve each iteration, evaluated with the same basis)."""
+    w = synth.random_workload(23, 3, 48, 10, [1.2, 0.5], 1e-6)
+    for b in ("c0", "c4", "c6"):
+        phi = np.vectorize(lambda e, b=b: o.wendland(b, e))
+        res = o.greedy(3, w.xs, w.ds, w.radius, w.eps, basis=b)
+        levels, alphas, _ = greedy_bruteforce(w.xs, w.ds, w.radius, w.eps, phi=phi)
+        got = [list(res.level(l)[0]) for l in range(res.n_levels_used)]
+        assert got == [list(c) for c in levels[: res.n_levels_used]], b
+        vol = o.volume(w.radius, [0.9, 0.9], res.level_off, w.xs[:, res.ctrl_idx], res.alpha, w.xs[:, :5],
+                       np.zeros(5), basis=b)
+        surf = sum(o.evaluate(w.radius[l], w.xs[:, res.level(l)[0]], res.level(l)[1], w.xs[:, :5], basis=b)
+                   for l in range(res.n_levels_used))
+        assert np.abs(vol - surf).max() <= 1e-15 * max(1.0, np.abs(surf).max()), b
+
+
 def pin_psi(o):
     """Wall-distance function of Section 4: 1 - xi on [0, 1), zero from xi = 1 on."""
     for xi, val in {0.0: 1.0, 0.25: 0.75, 0.5: 0.5, 0.75: 0.25, 1.0: 0.0, 2.0: 0.0}.items():
@@ -258,6 +340,29 @@ def pin_rigid_motion(o):
     dvr = o.volume(w.radius, [w.D] * 2, rt.level_off, (Q @ w.xs)[:, rt.ctrl_idx], rt.alpha,
                    Q @ w.xv, w.dwall)
     assert np.abs(dvr - Q @ dv0).max() <= 1e-10 * np.abs(dv0).max()
+
+
+def pin_support_distances(o):
+    """Section 4: D_l = k (dS_l)^max. A uniform displacement v gives D_0 = k |v|; later levels
+    use the maximum of the error left by the previous level, recomputed here from the level
+    interpolants (not from the greedy's own report)."""
+    import oracle as orc_mod
+
+    w = synth.random_workload(17, 2, 120, 10, [1.5, 0.4, 0.1], 1e-8)
+    v = np.array([[3e-3], [-4e-3]])
+    flat = np.repeat(v, w.n_s, axis=1)
+    res = o.greedy(2, w.xs, flat, [1.5], 1e-6, cap=20)
+    assert orc_mod.support_distances(5.0, flat, res) == [5.0 * 5e-3]
+    res = o.greedy(2, w.xs, w.ds, w.radius, w.eps)
+    assert res.n_levels_used == 3
+    D = orc_mod.support_distances(5.0, w.ds, res)
+    r = w.ds.copy()
+    for l in range(3):
+        want = 5.0 * np.sqrt((r ** 2).sum(axis=0)).max()
+        assert abs(D[l] - want) <= 1e-12 * want
+        c, a = res.level(l)
+        r = r - o.evaluate(w.radius[l], w.xs[:, c], a, w.xs)
+    assert D[0] > D[1] > D[2]
 
 
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

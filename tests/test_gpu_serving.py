@@ -218,3 +218,42 @@ def test_warm_start_reuses_resident_basis(gctx):
         assert torch.equal(d1, d2)
     # warm steps keep the earlier control points as their first ones
     assert np.array_equal(runs[0][1][0][: len(runs[0][0][0])][:5], runs[0][0][0][:5])
+
+
+def test_adaptive_support_distance(gctx, orc):
+    """Section 4's volume reduction with D_l = k (dS_l)^max (k = 5) per level: the serving path
+    derives D_l from the greedy's level maxima (equal to the oracle's within k times the FP64
+    residual bound); the result equals the oracle's volume update given those D_l, and every point
+    at or beyond max_l D_l is +0.0."""
+    import oracle as oracle_mod
+
+    w = synth.workload_cfg1(n_s=500, n_layers=40)
+    geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
+    dv = torch.full((2, w.n_v), float("nan"), dtype=torch.float64, device="cuda:0")
+    r = rbfdef.rbf_submit(gctx, geom, to_dev(w.ds), dv, w.radius, w.eps, [1.0] * w.n_levels, rho=w.rho,
+                          cap=w.cap_total(), seeds=w.seeds, precision="fp64", want_ctrl=True, d_factor=5.0)
+    info = rbfdef.rbf_wait(gctx, r)
+    assert info.state == rbfdef.REQ_DONE, info.result
+    ref = orc.greedy(2, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds)
+    cs = r.out
+    assert np.array_equal(cs.ctrl_idx[: cs.total].cpu().numpy(), ref.ctrl_idx)
+    D_ref = oracle_mod.support_distances(5.0, w.ds, ref)
+    D = cs.support_distances(5.0)
+    print(f"D_l oracle {D_ref} device {D}")
+    assert all(t > 0 for t in cs.level_seconds[: cs.n_levels_used])
+    xc = w.xs[:, ref.ctrl_idx]
+    used = ref.n_levels_used
+    S_surf = sum_magnitude(orc, w.radius[:used], ref.level_off[: used + 1], xc, ref.alpha, w.xs)
+    tol = 5.0 * fp64_bound(np.sqrt((w.ds ** 2).sum(0)).max(), S_surf)
+    assert len(D) == used and np.all(np.abs(np.array(D) - D_ref) <= tol)
+    want = orc.volume(w.radius[:used], D, ref.level_off[: used + 1], xc, ref.alpha, w.xv, w.dwall)
+    got = dv.cpu().numpy()
+    scale = np.sqrt((want ** 2).sum(0)).max()
+    S = sum_magnitude(orc, w.radius[:used], ref.level_off[: used + 1], xc, ref.alpha, w.xv, w.dwall, D)
+    err = np.sqrt(((got - want) ** 2).sum(0)).max()
+    print(f"adaptive-D volume error {err:.3e} (bound {fp64_bound(scale, S):.3e}); "
+          f"points per level {[int((w.dwall < d).sum()) for d in D]} of {w.n_v}")
+    assert err <= fp64_bound(scale, S)
+    far = w.dwall >= max(D)
+    assert np.all(got[:, far] == 0.0) and not np.any(np.signbit(got[:, far]))
+    rbfdef.rbf_geom_release(gctx, geom)

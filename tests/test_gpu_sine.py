@@ -1,0 +1,72 @@
+"""The paper's global (sinusoidal) deformation benchmarks (Results: dy = 0.01 sin(15 pi x) on the
+airfoil, eq. (27) on the swept wing) through the serving path, with the paper's parameters: one
+support radius on every level, reduction 0.1 per level, support distances D_l = 5 (dS_l)^max.
+
+Checks: identical control sets to the oracle's greedy; D_l equal to the oracle's within k times
+the FP64 bound of the level residual; the volume update equals the oracle's given those D_l (FP64
+bound); +0.0 beyond max_l D_l. Sizes: reduced meshes, and the full
+airfoil (4,000 surface points, 400,000 volume points), whose greedy the oracle still runs exactly.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as oracle_mod
+import synth
+from helpers import fp64_bound, sum_magnitude, to_dev
+from paper_2107_13887_amd import rbfdef
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(gctx, orc, w, sample=None):
+    print(f"case {w.name} n_s={w.n_s} n_v={w.n_v} levels {len(w.radius)}", flush=True)
+    geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
+    dv = torch.full((w.dim, w.n_v), float("nan"), dtype=torch.float64, device="cuda:0")
+    r = rbfdef.rbf_submit(gctx, geom, to_dev(w.ds), dv, w.radius, w.eps, [1.0] * w.n_levels, rho=w.rho,
+                          cap=w.cap_total(), seeds=w.seeds, precision="fp64", want_ctrl=True,
+                          d_factor=w.d_factor)
+    info = rbfdef.rbf_wait(gctx, r)
+    assert info.state == rbfdef.REQ_DONE, info.result
+    rbfdef.rbf_geom_release(gctx, geom)
+    ref = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds)
+    cs = r.out
+    print(f"levels {cs.level_off} oracle {list(ref.level_off)}")
+    assert np.array_equal(cs.ctrl_idx[: cs.total].cpu().numpy(), ref.ctrl_idx)
+    used = ref.n_levels_used
+    xc = w.xs[:, ref.ctrl_idx]
+    # D_l = k (dS_l)^max: the level maxima are residual maxima, equal within the FP64 bound of
+    # the residual (its terms cancel: sum |phi alpha| on the surface is far above dS_l).
+    D_ref = oracle_mod.support_distances(w.d_factor, w.ds, ref)
+    D = cs.support_distances(w.d_factor)
+    S_surf = sum_magnitude(orc, w.radius[:used], ref.level_off[: used + 1], xc, ref.alpha, w.xs)
+    tol = w.d_factor * fp64_bound(np.sqrt((w.ds ** 2).sum(0)).max(), S_surf)
+    assert len(D) == used and np.all(np.abs(np.array(D) - D_ref) <= tol), (D, D_ref, tol)
+    got = dv.cpu().numpy()
+    far = w.dwall >= max(D)
+    assert np.all(got[:, far] == 0.0) and not np.any(np.signbit(got[:, far]))
+    pick = np.arange(w.n_v) if sample is None else sample
+    want = orc.volume(w.radius[:used], D, ref.level_off[: used + 1], xc, ref.alpha, w.xv[:, pick],
+                      w.dwall[pick])
+    scale = max(np.sqrt((want ** 2).sum(0)).max(), 1e-300)
+    S = sum_magnitude(orc, w.radius[:used], ref.level_off[: used + 1], xc, ref.alpha, w.xv[:, pick],
+                      w.dwall[pick], D)
+    err = np.sqrt(((got[:, pick] - want) ** 2).sum(0)).max()
+    print(f"volume error {err:.3e} (bound {fp64_bound(scale, S):.3e}); D {['%.3g' % d for d in D]}")
+    assert err <= fp64_bound(scale, S)
+
+
+def test_sine_airfoil_reduced(gctx, orc):
+    _run(gctx, orc, synth.workload_sine2d(n_s=600, n_layers=20))
+
+
+def test_sine_wing_reduced(gctx, orc):
+    _run(gctx, orc, synth.workload_sine3d(n_chord=60, n_span=30, n_layers=8, cap=1500))
+
+
+@pytest.mark.slow
+def test_sine_airfoil_full(gctx, orc):
+    w = synth.workload_sine2d()
+    inside = np.flatnonzero(w.dwall < 0.05 + 1e-9)
+    pick = np.random.default_rng(3).choice(inside, min(4000, inside.size), replace=False)
+    _run(gctx, orc, w, sample=pick)
