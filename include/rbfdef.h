@@ -47,6 +47,13 @@ typedef int32_t rbf_status;
 #define RBF_MIXED 1  /* volume kernel sums in FP32 on locally shifted coordinates with an FP64
                         accumulator; greedy factor, convergence check and residuals stay FP64 */
 
+/* Basis functions phi(eta), eta = ||r - r_c|| / R, the Wendland functions of Table 1, each zero
+ * for eta >= 1 and 1 at eta = 0. C2 (eq. (2)) is the paper's choice and the zero default. */
+#define RBF_WENDLAND_C2 0   /* (1 - eta)^4 (4 eta + 1) */
+#define RBF_WENDLAND_C0 1   /* (1 - eta)^2 */
+#define RBF_WENDLAND_C4 2   /* (1 - eta)^6 (35/3 eta^2 + 6 eta + 1) */
+#define RBF_WENDLAND_C6 3   /* (1 - eta)^8 (32 eta^3 + 25 eta^2 + 8 eta + 1) */
+
 #define RBF_STOP_SKIPPED (-1)     /* level not run: an earlier level already met eps_abs */
 #define RBF_STOP_EPS 0            /* max ||E|| fell below the level's target */
 #define RBF_STOP_CAP 1            /* max_ctrl_total reached */
@@ -100,6 +107,7 @@ typedef struct {
     const int64_t *seed_idx;        /* host: seed point indices of all levels, CSR by seed_off */
     const int32_t *seed_off;        /* host [n_levels + 1]; NULL = paper default {0} at level 0 */
     int32_t precision;              /* RBF_FP64 or RBF_MIXED */
+    int32_t basis;                  /* RBF_WENDLAND_*; requests use it for the volume update too */
 } rbf_greedy_params;
 
 /* Result of a greedy selection. The caller sets the four device pointers and `capacity`
@@ -139,7 +147,8 @@ rbf_status rbf_greedy_select(rbf_ctx ctx, const rbf_greedy_params *params, int64
  * matrix cores) and triangular solves. xc, dsc, alpha: device [dim][n_c]. Blocking.
  * RBF_E_NOT_SPD when a pivot is not positive (repeated or numerically coincident points). */
 rbf_status rbf_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c,
-                             const double *xc, const double *dsc, double *alpha, void *stream);
+                             const double *xc, const double *dsc, double *alpha, int32_t basis,
+                             void *stream);
 
 /* Volume update with wall-distance reduction, eqs. (19) and (23):
  *   dv_v = sum_l psi(dwall_v / D_l) sum_{c in level l} phi(||xv_v - xc_c|| / radius_l) alpha_c
@@ -147,12 +156,13 @@ rbf_status rbf_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_
  * and are skipped (the volume point reduction of Section 4).
  * radius, D: host [n_levels]; level_off: host [n_levels + 1] offsets into xc/alpha;
  * xc, alpha: device [dim][ld_ctrl]; xv: device [dim][n_v]; dwall: device [n_v];
- * dv: device [dim][n_v] output (fully written). precision: RBF_FP64 or RBF_MIXED.
- * Enqueued on `stream`; returns before the device work finishes. */
+ * dv: device [dim][n_v] output (fully written). precision: RBF_FP64 or RBF_MIXED; basis:
+ * RBF_WENDLAND_*. Enqueued on `stream`; returns before the device work finishes. */
 rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
                              const double *D, const int32_t *level_off, int64_t ld_ctrl,
                              const double *xc, const double *alpha, int64_t n_v, const double *xv,
-                             const double *dwall, double *dv, int32_t precision, void *stream);
+                             const double *dwall, double *dv, int32_t precision, int32_t basis,
+                             void *stream);
 
 /* Interpolant evaluation, eq. (1) with the support of eq. (2), at n_p points:
  *   out_k(p) = base_k(p) - sign * sum_c phi(||x_p - xc_c|| / radius) alpha_k,c
@@ -162,7 +172,7 @@ rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const d
 rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, int64_t ld_ctrl,
                         const double *xc, const double *alpha, int64_t n_p, const double *xp,
                         const double *base, double sign, double *out, int32_t precision,
-                        void *stream);
+                        int32_t basis, void *stream);
 
 /* ---------------------------------------------------------------------------------------------
  * Serving: resident geometries and asynchronous deformation requests with continuous batching.
@@ -216,7 +226,7 @@ typedef struct {
 rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, const double *radius,
                                   const double *D, const int32_t *level_off, int64_t ld_ctrl,
                                   const double *xc, const double *alpha, double *dv,
-                                  int32_t precision, void *stream);
+                                  int32_t precision, int32_t basis, void *stream);
 
 /* Non-blocking. RBF_E_NOMEM if the request could never fit the budget. */
 rbf_status rbf_submit(rbf_ctx ctx, const rbf_request *req, rbf_ticket *out);

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 
+#include "basis.h"
 #include "internal.h"
 
 namespace rbf {
@@ -221,6 +222,7 @@ rbf_status validate_params(const rbf_greedy_params &p, int64_t n_s)
     if (p.max_ctrl_total < 1) return fail(RBF_E_INVALID, "max_ctrl_total must be >= 1");
     if (p.precision != RBF_FP64 && p.precision != RBF_MIXED)
         return fail(RBF_E_INVALID, "unknown precision %d", p.precision);
+    if (!basis_valid(p.basis)) return fail(RBF_E_INVALID, "unknown basis %d", p.basis);
     if (p.seed_off) {
         if (p.seed_off[0] != 0) return fail(RBF_E_INVALID, "seed_off[0] must be 0");
         for (int l = 0; l < p.n_levels; ++l) {
@@ -363,7 +365,7 @@ rbf_status rbf_greedy_select(rbf_ctx ctx, const rbf_greedy_params *params, int64
 }
 
 rbf_status rbf_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, const double *xc,
-                             const double *dsc, double *alpha, void *stream)
+                             const double *dsc, double *alpha, int32_t basis, void *stream)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
     if (dim != 2 && dim != 3) return fail(RBF_E_INVALID, "dim must be 2 or 3");
@@ -371,7 +373,8 @@ rbf_status rbf_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_
     if (n_c < 1 || n_c > 65536) return fail(RBF_E_INVALID, "n_c must be in 1..65536");
     if (!xc || !dsc || !alpha) return fail(RBF_E_INVALID, "NULL device array");
     RBF_HIP(hipSetDevice(ctx->device));
-    return run_solve_weights(ctx, dim, radius, n_c, xc, dsc, alpha, (hipStream_t)stream);
+    if (!basis_valid(basis)) return fail(RBF_E_INVALID, "unknown basis %d", basis);
+    return run_solve_weights(ctx, dim, radius, n_c, xc, dsc, alpha, basis, (hipStream_t)stream);
 }
 
 static rbf_status check_levels(int32_t n_levels, const double *radius, const double *D,
@@ -394,7 +397,8 @@ static rbf_status check_levels(int32_t n_levels, const double *radius, const dou
 rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
                              const double *D, const int32_t *level_off, int64_t ld_ctrl,
                              const double *xc, const double *alpha, int64_t n_v, const double *xv,
-                             const double *dwall, double *dv, int32_t precision, void *stream)
+                             const double *dwall, double *dv, int32_t precision, int32_t basis,
+                             void *stream)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
     if (dim != 2 && dim != 3) return fail(RBF_E_INVALID, "dim must be 2 or 3");
@@ -402,6 +406,7 @@ rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const d
     RBF_TRY(check_levels(n_levels, radius, D, level_off, ld_ctrl));
     if (n_v < 0 || n_v > (int64_t(1) << 31) - 1) return fail(RBF_E_INVALID, "n_v out of range");
     if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_E_INVALID, "bad precision");
+    if (!basis_valid(basis)) return fail(RBF_E_INVALID, "unknown basis %d", basis);
     if (n_v == 0) return RBF_OK;
     if (!xv || !dwall || !dv || (level_off[n_levels] > level_off[0] && (!xc || !alpha)))
         return fail(RBF_E_INVALID, "NULL device array");
@@ -420,12 +425,14 @@ rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const d
     pb.out = dv;
     pb.sign = -1.0;
     pb.precision = precision;
+    pb.basis = basis;
     return run_kernel_sum(ctx, pb, (hipStream_t)stream);
 }
 
 rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, int64_t ld_ctrl,
                         const double *xc, const double *alpha, int64_t n_p, const double *xp,
-                        const double *base, double sign, double *out, int32_t precision, void *stream)
+                        const double *base, double sign, double *out, int32_t precision, int32_t basis,
+                        void *stream)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
     if (dim != 2 && dim != 3) return fail(RBF_E_INVALID, "dim must be 2 or 3");
@@ -433,6 +440,7 @@ rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, in
     if (n_c < 0 || ld_ctrl < n_c) return fail(RBF_E_INVALID, "n_c/ld_ctrl out of range");
     if (n_p < 0 || n_p > (int64_t(1) << 31) - 1) return fail(RBF_E_INVALID, "n_p out of range");
     if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_E_INVALID, "bad precision");
+    if (!basis_valid(basis)) return fail(RBF_E_INVALID, "unknown basis %d", basis);
     if (!std::isfinite(sign)) return fail(RBF_E_INVALID, "sign must be finite");
     if (n_p == 0) return RBF_OK;
     if (!xp || !out || (n_c > 0 && (!xc || !alpha))) return fail(RBF_E_INVALID, "NULL device array");
@@ -450,6 +458,7 @@ rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, in
     pb.sign = sign;
     pb.out = out;
     pb.precision = precision;
+    pb.basis = basis;
     return run_kernel_sum(ctx, pb, (hipStream_t)stream);
 }
 

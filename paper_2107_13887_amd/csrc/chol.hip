@@ -10,6 +10,7 @@
 // A non-positive pivot raises a device flag reported as RBF_E_NOT_SPD.
 #include <cmath>
 
+#include "basis.h"
 #include "internal.h"
 
 namespace rbf {
@@ -34,7 +35,7 @@ __device__ __forceinline__ double sqrt_pos(double a)
 // rows/columns beyond n get the identity so the padded factorization stays well defined.
 template <int DIM>
 __global__ __launch_bounds__(256) void c_build(const double *xc, int64_t n, int64_t lda,
-                                               double inv_r, double *A)
+                                               double inv_r, int32_t basis, double *A)
 {
     for (int64_t i = blockIdx.x; i < lda; i += gridDim.x)
     for (int64_t j = threadIdx.x; j <= i; j += 256) {
@@ -46,10 +47,7 @@ __global__ __launch_bounds__(256) void c_build(const double *xc, int64_t n, int6
                 double d = (xc[k * n + i] - xc[k * n + j]) * inv_r;
                 r2 = __builtin_fma(d, d, r2);
             }
-            double eta = sqrt_pos(fmax(r2, 1e-200));
-            double t = fmax(1.0 - eta, 0.0);
-            double t2 = t * t;
-            v = (t2 * t2) * __builtin_fma(4.0, eta, 1.0);
+            v = wendland(basis, sqrt_pos(fmax(r2, 1e-200)));
         } else {
             v = (i == j) ? 1.0 : 0.0;
         }
@@ -283,7 +281,7 @@ __global__ __launch_bounds__(256) void c_bwd(const double *A, int64_t lda, doubl
 
 template <int DIM>
 rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, const double *dsc,
-                      double *alpha, hipStream_t s)
+                      double *alpha, int32_t basis, hipStream_t s)
 {
     Pool *pool = ctx->pool.get();
     const int64_t lda = ((n + NB - 1) / NB) * NB;
@@ -297,7 +295,7 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
     double *A = bA.as<double>();
     RBF_HIP(hipMemsetAsync(bFlag.ptr, 0, sizeof(int32_t), s));
     hipLaunchKernelGGL(c_build<DIM>, dim3((unsigned)std::min<int64_t>(lda, 8192)), dim3(256), 0, s,
-                       xc, n, lda, 1.0 / radius, A);
+                       xc, n, lda, 1.0 / radius, basis, A);
     for (int64_t kb = 0; kb < nblk; ++kb) {
         const int64_t k0 = kb * NB, rest = nblk - kb - 1;
         hipLaunchKernelGGL(c_diag, dim3(1), dim3(256), 0, s, A, lda, k0, bInv.as<double>(), bFlag.as<int32_t>());
@@ -332,10 +330,10 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
 }  // namespace
 
 rbf_status run_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, const double *xc,
-                             const double *dsc, double *alpha, hipStream_t s)
+                             const double *dsc, double *alpha, int32_t basis, hipStream_t s)
 {
-    return dim == 2 ? solve_impl<2>(ctx, radius, n_c, xc, dsc, alpha, s)
-                    : solve_impl<3>(ctx, radius, n_c, xc, dsc, alpha, s);
+    return dim == 2 ? solve_impl<2>(ctx, radius, n_c, xc, dsc, alpha, basis, s)
+                    : solve_impl<3>(ctx, radius, n_c, xc, dsc, alpha, basis, s);
 }
 
 }  // namespace rbf

@@ -29,6 +29,7 @@
 #include <cstring>
 #include <vector>
 
+#include "basis.h"
 #include "internal.h"
 
 namespace cg = cooperative_groups;
@@ -63,6 +64,7 @@ struct GArgs {
     const double *xs;
     int64_t n_s;
     double R;
+    int32_t basis;       // RBF_WENDLAND_*
     double *V;           // [cols][n_s] column-major Newton basis
     double *Lpack;       // packed lower factor, row n at n (n + 1) / 2
     double *coef;        // [DIM][ld_coef] Newton coefficients y
@@ -110,22 +112,24 @@ __device__ __forceinline__ double norm2_plain(const double *v, int64_t ld, int64
     return s;
 }
 
-// phi(||x_i - x_j|| / R) term by term as the textbook formula (no contraction); only a few of
-// these are computed per iteration.
+// phi(||x_i - x_j|| / R) of the selected basis (Table 1), distance term by term with no
+// contraction; only a few of these are computed per iteration.
 template <int DIM>
-__device__ __forceinline__ double phi_pair(const double *xs, int64_t ld, int64_t i, int64_t j, double R)
+__device__ __forceinline__ double phi_pair(const double *xs, int64_t ld, int64_t i, int64_t j, double R,
+                                           int32_t basis)
 {
-#pragma clang fp contract(off)
     double s = 0.0;
+    {
+#pragma clang fp contract(off)
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        double d = xs[k * ld + i] - xs[k * ld + j];
-        s = s + d * d;
+        for (int k = 0; k < DIM; ++k) {
+            double d = xs[k * ld + i] - xs[k * ld + j];
+            s = s + d * d;
+        }
     }
     double eta = sqrt(s) / R;
     if (eta >= 1.0) return 0.0;
-    double t = 1.0 - eta;
-    return t * t * t * t * (4.0 * eta + 1.0);
+    return wendland(basis, eta);
 }
 
 __device__ __forceinline__ void wave_argmax(double &m2, int64_t &idx)
@@ -326,7 +330,7 @@ __device__ void update_tile(const GArgs &a, int64_t tile, int64_t n, int64_t p, 
             double dot = u.psum[0][lane];
 #pragma unroll
             for (int k = 1; k < UWAVES; ++k) dot += u.psum[k][lane];
-            const double v = (phi_pair<DIM>(a.xs, a.n_s, i, p, a.R) - dot) / d;
+            const double v = (phi_pair<DIM>(a.xs, a.n_s, i, p, a.R, a.basis) - dot) / d;
             a.V[n * ldV + i] = v;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) a.E[k * a.n_s + i] = __builtin_fma(-c[k], v, a.E[k * a.n_s + i]);
@@ -783,6 +787,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     a.st = st;
     a.xs = xs;
     a.n_s = n_s;
+    a.basis = prm.basis;
     a.V = bV.as<double>();
     a.Lpack = bL.as<double>();
     a.coef = bCoef.as<double>();
@@ -822,7 +827,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         if (warm && l < (int)warm->size()) {
             const LevelCache &lc = (*warm)[l];
             const int64_t n0 = lc.n;
-            const bool same = n0 > 0 && n0 == a.n_seeds && lc.radius == Rl && n0 <= a.cap_level &&
+            const bool same = n0 > 0 && n0 == a.n_seeds && lc.radius == Rl && lc.basis == prm.basis &&
+                              n0 <= a.cap_level &&
                               std::equal(lc.ctrl.begin(), lc.ctrl.end(), seeds_h.begin() + seed_off[l]);
             if (same) {
                 RBF_HIP(hipMemcpyAsync(a.V, lc.V.ptr, sizeof(double) * n0 * n_s, hipMemcpyDeviceToDevice, s));
@@ -926,6 +932,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
             pb.sign = 1.0;
             pb.out = R2;
             pb.precision = RBF_FP64;
+            pb.basis = prm.basis;
             RBF_TRY(run_kernel_sum(ctx, pb, s));
             std::swap(R, R2);
         }
@@ -944,6 +951,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
                 RBF_HIP(hipMemcpyAsync(lc.ctrl.data(), a.ctrl, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
                 lc.n = n;
                 lc.radius = Rl;
+                lc.basis = prm.basis;
             } else {
                 lc.V.release_after(s);   // no room for this level's copy: leave it uncached
                 lc.L.release_after(s);

@@ -99,6 +99,7 @@ struct LevelCache {
     DevBuf V, L;
     int64_t n = 0;          // control points (columns)
     double radius = 0.0;
+    int32_t basis = RBF_WENDLAND_C2;
     std::vector<int64_t> ctrl;   // host copy, selection order
 };
 
@@ -187,6 +188,7 @@ struct SumProblem {
     double *out = nullptr;        // [dim][ld_out], fully written
     int64_t ld_out = 0;           // 0: n_p
     int32_t precision = RBF_FP64;
+    int32_t basis = RBF_WENDLAND_C2;
     // Resident geometry: points (xp, dwall) are stored in blocks ordered by their smallest wall
     // distance, the reduced volume lies in the prefix [0, n_active), and the result of slot v goes
     // to out[.][perm[v]] (perm: stored -> caller order, -1 for padding); points with psi = 0 get
@@ -212,7 +214,8 @@ uint64_t cache_bytes(const std::vector<LevelCache> &levels, int64_t n_s);
 
 // ---- dense solves (chol.hip) --------------------------------------------------------------------
 rbf_status run_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c,
-                             const double *xc, const double *dsc, double *alpha, hipStream_t s);
+                             const double *xc, const double *dsc, double *alpha, int32_t basis,
+                             hipStream_t s);
 
 // ---- validation helpers (capi.cpp) ---------------------------------------------------------------
 rbf_status validate_params(const rbf_greedy_params &p, int64_t n_s);

@@ -24,6 +24,7 @@
 //     Goldschmidt step (error ~1.5 e^2) and one Newton correction (error ~1.5 e^3);
 //   * mixed precision: the pair arithmetic runs in FP32 on coordinates shifted to a per-workgroup
 //     origin (the workgroup's first point), the basis value is widened and accumulated in FP64.
+#include "basis.h"
 #include "internal.h"
 
 namespace rbf {
@@ -89,8 +90,8 @@ __device__ __forceinline__ void split_range(const SumLevel &L, int s, int S, int
     ce = L.c_begin + (nc * (s + 1)) / S;
 }
 
-// One pair in FP64: phi(|q - c|) for coordinates already scaled by 1/R (eq. (2)).
-template <int DIM>
+// One pair in FP64: phi(|q - c|) for coordinates already scaled by 1/R (Table 1).
+template <int DIM, int BASIS>
 __device__ __forceinline__ double pair_f64(const double (&q)[DIM], const double *c)
 {
     double d0 = q[0] - c[0];
@@ -102,11 +103,10 @@ __device__ __forceinline__ double pair_f64(const double (&q)[DIM], const double 
     }
     double eta = sqrt_goldschmidt(r2);
     double t = fmax(1.0 - eta, 0.0);
-    double t2 = t * t;
-    return (t2 * t2) * __builtin_fma(4.0, eta, 1.0);
+    return wendland_t<BASIS, double>(eta, t);
 }
 
-template <int DIM>
+template <int DIM, int BASIS>
 __device__ __forceinline__ float pair_f32(const float (&q)[DIM], const float *c)
 {
     float d0 = q[0] - c[0];
@@ -118,11 +118,10 @@ __device__ __forceinline__ float pair_f32(const float (&q)[DIM], const float *c)
     }
     float eta = __builtin_amdgcn_sqrtf(r2);
     float t = fmaxf(1.0f - eta, 0.0f);
-    float t2 = t * t;
-    return (t2 * t2) * __builtin_fmaf(4.0f, eta, 1.0f);
+    return wendland_t<BASIS, float>(eta, t);
 }
 
-template <int DIM, int P, bool MIXED>
+template <int DIM, int P, bool MIXED, int BASIS>
 __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
 {
     // FP64: per control DIM scaled coordinates then DIM weights. Mixed: 4 floats of shifted
@@ -282,7 +281,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                     for (int k = 0; k < DIM; ++k) cpos[k] = reinterpret_cast<const float *>(cc)[k];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        const double ph = (double)pair_f32<DIM>(q32[p], cpos);
+                        const double ph = (double)pair_f32<DIM, BASIS>(q32[p], cpos);
 #pragma unroll
                         for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
                     }
@@ -292,7 +291,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                     for (int k = 0; k < DIM; ++k) cpos[k] = cc[k];
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        const double ph = pair_f64<DIM>(q64[p], cpos);
+                        const double ph = pair_f64<DIM, BASIS>(q64[p], cpos);
 #pragma unroll
                         for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
                     }
@@ -416,21 +415,31 @@ __global__ __launch_bounds__(BLOCK) void reduce_scatter(const double *d, int64_t
     }
 }
 
-template <int DIM, int P>
+template <int DIM, int P, int BASIS>
 void launch_sum(const KArgs &a, dim3 grid, bool mixed, hipStream_t s)
 {
     if (mixed)
-        hipLaunchKernelGGL((ksum_kernel<DIM, P, true>), grid, dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((ksum_kernel<DIM, P, true, BASIS>), grid, dim3(BLOCK), 0, s, a);
     else
-        hipLaunchKernelGGL((ksum_kernel<DIM, P, false>), grid, dim3(BLOCK), 0, s, a);
+        hipLaunchKernelGGL((ksum_kernel<DIM, P, false, BASIS>), grid, dim3(BLOCK), 0, s, a);
+}
+
+template <int DIM, int BASIS>
+void launch_sum_p(const KArgs &a, dim3 grid, int P, bool mixed, hipStream_t s)
+{
+    if (P == 1) launch_sum<DIM, 1, BASIS>(a, grid, mixed, s);
+    else launch_sum<DIM, 2, BASIS>(a, grid, mixed, s);
 }
 
 template <int DIM>
-void launch_sum_p(const KArgs &a, dim3 grid, int P, bool mixed, hipStream_t s)
+void launch_sum_b(const KArgs &a, dim3 grid, int P, bool mixed, int32_t basis, hipStream_t s)
 {
-    if (P == 1) launch_sum<DIM, 1>(a, grid, mixed, s);
-    else if (P == 2) launch_sum<DIM, 2>(a, grid, mixed, s);
-    else launch_sum<DIM, 4>(a, grid, mixed, s);
+    switch (basis) {
+    case RBF_WENDLAND_C0: launch_sum_p<DIM, RBF_WENDLAND_C0>(a, grid, P, mixed, s); break;
+    case RBF_WENDLAND_C4: launch_sum_p<DIM, RBF_WENDLAND_C4>(a, grid, P, mixed, s); break;
+    case RBF_WENDLAND_C6: launch_sum_p<DIM, RBF_WENDLAND_C6>(a, grid, P, mixed, s); break;
+    default: launch_sum_p<DIM, RBF_WENDLAND_C2>(a, grid, P, mixed, s); break;
+    }
 }
 
 int env_int(const char *name, int dflt)
@@ -497,7 +506,7 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     // workgroups, which balances better when there are few blocks (the cost of a block varies
     // with the number of controls near it).
     int P = env_int("RBF_KSUM_P", n_rows < (int64_t)8 * ctx->n_cu * VBLOCK ? 1 : 2);
-    if (P != 1 && P != 2 && P != 4) P = 2;
+    if (P != 1 && P != 2) P = 2;
     const int64_t nbx = (n_rows + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
     const int64_t target = (int64_t)env_int("RBF_KSUM_BLOCKS", 8 * ctx->n_cu);
     // Split only while every split keeps at least 128 controls: a split re-reads the points and
@@ -517,8 +526,8 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     a.pairs = ctx->timers.counter(name);
     hipEvent_t t0;
     ctx->timers.begin(&t0, s);
-    if (DIM == 2) launch_sum_p<2>(a, grid, P, mixed, s);
-    else launch_sum_p<3>(a, grid, P, mixed, s);
+    if (DIM == 2) launch_sum_b<2>(a, grid, P, mixed, pb.basis, s);
+    else launch_sum_b<3>(a, grid, P, mixed, pb.basis, s);
     RBF_HIP(hipGetLastError());
     ctx->timers.end(name, t0, s);
     if (S > 1) {

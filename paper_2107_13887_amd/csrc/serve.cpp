@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "basis.h"
 #include "internal.h"
 
 namespace rbf {
@@ -590,6 +591,7 @@ rbf_status Server::run(Req &q, hipStream_t s)
     pb.out = q.r.dv;
     pb.sign = -1.0;
     pb.precision = p.precision;
+    pb.basis = p.basis;
     RBF_TRY(run_kernel_sum(ctx_, pb, s));
     RBF_HIP(hipStreamSynchronize(s));
     // Remember the control sets for the next icing step on this geometry.
@@ -685,7 +687,7 @@ rbf_status rbf_geom_create(rbf_ctx ctx, int32_t dim, int64_t n_s, const double *
 rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, const double *radius,
                                   const double *D, const int32_t *level_off, int64_t ld_ctrl,
                                   const double *xc, const double *alpha, double *dv,
-                                  int32_t precision, void *stream)
+                                  int32_t precision, int32_t basis, void *stream)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
     Geometry *g = nullptr;
@@ -707,6 +709,7 @@ rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, 
     }
     if (level_off[n_levels] > ld_ctrl) return fail(RBF_E_INVALID, "level_off exceeds ld_ctrl");
     if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_E_INVALID, "bad precision");
+    if (!basis_valid(basis)) return fail(RBF_E_INVALID, "unknown basis %d", basis);
     if (g->n_v == 0) return RBF_OK;
     if (!dv || (level_off[n_levels] > level_off[0] && (!xc || !alpha))) return fail(RBF_E_INVALID, "NULL device array");
     RBF_HIP(hipSetDevice(ctx->device));
@@ -726,6 +729,7 @@ rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, 
     pb.out = dv;
     pb.sign = -1.0;
     pb.precision = precision;
+    pb.basis = basis;
     return run_kernel_sum(ctx, pb, (hipStream_t)stream);
 }
 

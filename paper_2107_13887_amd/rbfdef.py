@@ -21,6 +21,14 @@ HEADER = os.path.join(ROOT, "include", "rbfdef.h")
 RBF_OK, RBF_W_CAP, RBF_W_BREAKDOWN = 0, 1, 2
 RBF_E_INVALID, RBF_E_NOMEM, RBF_E_NOT_SPD, RBF_E_DEVICE, RBF_E_NOT_FOUND, RBF_E_BUSY = -1, -2, -3, -4, -5, -6
 RBF_FP64, RBF_MIXED = 0, 1
+RBF_WENDLAND_C2, RBF_WENDLAND_C0, RBF_WENDLAND_C4, RBF_WENDLAND_C6 = 0, 1, 2, 3
+BASES = {"c2": RBF_WENDLAND_C2, "c0": RBF_WENDLAND_C0, "c4": RBF_WENDLAND_C4, "c6": RBF_WENDLAND_C6}
+
+
+def _basis(name: str) -> int:
+    if name not in BASES:
+        raise ValueError(f"unknown basis {name!r}; one of {sorted(BASES)}")
+    return BASES[name]
 MAX_LEVELS = 8
 RBF_STOP_SKIPPED, RBF_STOP_EPS, RBF_STOP_CAP, RBF_STOP_ALL_SELECTED, RBF_STOP_BREAKDOWN = -1, 0, 1, 2, 3
 STOP_NAMES = {-1: "skipped", 0: "eps", 1: "cap", 2: "all_selected", 3: "breakdown"}
@@ -34,7 +42,7 @@ class rbf_greedy_params(ctypes.Structure):
     _fields_ = [("dim", _i32), ("n_levels", _i32), ("radius", _f64 * MAX_LEVELS),
                 ("eps_abs", _f64), ("level_reduction", _f64), ("max_ctrl_total", _i64),
                 ("seed_idx", ctypes.POINTER(_i64)), ("seed_off", ctypes.POINTER(_i32)),
-                ("precision", _i32)]
+                ("precision", _i32), ("basis", _i32)]
 
 
 class rbf_ctrl_set(ctypes.Structure):
@@ -64,14 +72,15 @@ _SIGS = {
     "rbf_ctx_bytes_in_use": (_u64, [_vp]),
     "rbf_greedy_select": (_i32, [_vp, ctypes.POINTER(rbf_greedy_params), _i64, _vp, _vp,
                                  ctypes.POINTER(rbf_ctrl_set), _vp]),
-    "rbf_solve_weights": (_i32, [_vp, _i32, _f64, _i64, _vp, _vp, _vp, _vp]),
+    "rbf_solve_weights": (_i32, [_vp, _i32, _f64, _i64, _vp, _vp, _vp, _i32, _vp]),
     "rbf_volume_update": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
-                                 ctypes.POINTER(_i32), _i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _vp]),
-    "rbf_evaluate": (_i32, [_vp, _i32, _f64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _f64, _vp, _i32, _vp]),
+                                 ctypes.POINTER(_i32), _i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _vp]),
+    "rbf_evaluate": (_i32, [_vp, _i32, _f64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _f64, _vp, _i32, _i32,
+                            _vp]),
     "rbf_geom_create": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_vp)]),
     "rbf_geom_release": (_i32, [_vp, _vp]),
     "rbf_geom_volume_update": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
-                                      ctypes.POINTER(_i32), _i64, _vp, _vp, _vp, _i32, _vp]),
+                                      ctypes.POINTER(_i32), _i64, _vp, _vp, _vp, _i32, _i32, _vp]),
     "rbf_submit": (_i32, [_vp, ctypes.POINTER(rbf_request), ctypes.POINTER(_u64)]),
     "rbf_poll": (_i32, [_vp, _u64, ctypes.POINTER(rbf_req_info)]),
     "rbf_wait": (_i32, [_vp, _u64, ctypes.POINTER(rbf_req_info)]),
@@ -230,7 +239,7 @@ class CtrlSet:
 
 def make_params(dim: int, radius: Sequence[float], eps: float, rho: float = 0.1, cap: int = 0,
                 seeds: Optional[Sequence[Sequence[int]]] = None, precision: str = "fp64",
-                n_s: Optional[int] = None):
+                n_s: Optional[int] = None, basis: str = "c2"):
     """Build rbf_greedy_params; the returned tuple keeps the seed arrays alive."""
     p = rbf_greedy_params()
     p.dim = dim
@@ -241,6 +250,7 @@ def make_params(dim: int, radius: Sequence[float], eps: float, rho: float = 0.1,
     p.level_reduction = float(rho)
     p.max_ctrl_total = int(cap if cap > 0 else (n_s or 1) * len(radius))
     p.precision = RBF_MIXED if precision == "mixed" else RBF_FP64
+    p.basis = _basis(basis)
     keep = []
     if seeds is not None:
         lv = [list(seeds[l]) if l < len(seeds) else [] for l in range(len(radius))]
@@ -257,11 +267,11 @@ def make_params(dim: int, radius: Sequence[float], eps: float, rho: float = 0.1,
 
 def rbf_greedy_select(ctx: int, xs, ds, radius: Sequence[float], eps: float, rho: float = 0.1,
                       cap: int = 0, seeds=None, precision: str = "fp64", want_residual: bool = True,
-                      stream=None) -> CtrlSet:
+                      stream=None, basis: str = "c2") -> CtrlSet:
     import torch
 
     dim, n_s = xs.shape
-    p, keep = make_params(dim, radius, eps, rho, cap, seeds, precision, n_s)
+    p, keep = make_params(dim, radius, eps, rho, cap, seeds, precision, n_s, basis)
     pxs, _ = _dev(xs, "xs", dim, n_s)
     pds, _ = _dev(ds, "ds", dim, n_s)
     capacity = int(p.max_ctrl_total)
@@ -289,7 +299,7 @@ def rbf_greedy_select(ctx: int, xs, ds, radius: Sequence[float], eps: float, rho
                    level_seconds=[out.level_seconds[l] for l in range(len(radius))])
 
 
-def rbf_solve_weights(ctx: int, radius: float, xc, dsc, alpha=None, stream=None):
+def rbf_solve_weights(ctx: int, radius: float, xc, dsc, alpha=None, stream=None, basis: str = "c2"):
     import torch
 
     dim, n_c = xc.shape
@@ -298,13 +308,14 @@ def rbf_solve_weights(ctx: int, radius: float, xc, dsc, alpha=None, stream=None)
     if alpha is None:
         alpha = torch.empty((dim, n_c), dtype=torch.float64, device=xc.device)
     pa, _ = _dev(alpha, "alpha", dim, n_c)
-    _check(lib().rbf_solve_weights(ctx, dim, float(radius), n_c, pxc, pds, pa, _stream(stream)),
+    _check(lib().rbf_solve_weights(ctx, dim, float(radius), n_c, pxc, pds, pa, _basis(basis), _stream(stream)),
            "rbf_solve_weights")
     return alpha
 
 
 def rbf_volume_update(ctx: int, radius: Sequence[float], D: Sequence[float], level_off: Sequence[int],
-                      xc, alpha, xv, dwall, dv=None, precision: str = "fp64", stream=None):
+                      xc, alpha, xv, dwall, dv=None, precision: str = "fp64", stream=None,
+                      basis: str = "c2"):
     """Enqueue the psi-weighted volume update; returns dv (written asynchronously on the stream)."""
     import torch
 
@@ -328,13 +339,13 @@ def rbf_volume_update(ctx: int, radius: Sequence[float], D: Sequence[float], lev
     d = (_f64 * nl)(*[float(x) for x in D])
     off = (_i32 * (nl + 1))(*[int(x) for x in level_off])
     _check(lib().rbf_volume_update(ctx, dim, nl, r, d, off, ldc, pxc, pa, n_v, pxv, pd, pdv,
-                                   RBF_MIXED if precision == "mixed" else RBF_FP64, _stream(stream)),
+                                   RBF_MIXED if precision == "mixed" else RBF_FP64, _basis(basis), _stream(stream)),
            "rbf_volume_update")
     return dv
 
 
 def rbf_evaluate(ctx: int, radius: float, xc, alpha, xp, base=None, sign: float = -1.0, out=None,
-                 precision: str = "fp64", stream=None):
+                 precision: str = "fp64", stream=None, basis: str = "c2"):
     """out = base - sign * sum_c phi(||x_p - xc|| / R) alpha_c (plain interpolant by default)."""
     import torch
 
@@ -350,7 +361,7 @@ def rbf_evaluate(ctx: int, radius: float, xc, alpha, xp, base=None, sign: float 
         out = torch.empty((dim, n_p), dtype=torch.float64, device=xp.device)
     po, _ = _dev(out, "out", dim, n_p)
     _check(lib().rbf_evaluate(ctx, dim, float(radius), n_c, ldc, pxc, pa, n_p, pxp, pb, float(sign), po,
-                              RBF_MIXED if precision == "mixed" else RBF_FP64, _stream(stream)),
+                              RBF_MIXED if precision == "mixed" else RBF_FP64, _basis(basis), _stream(stream)),
            "rbf_evaluate")
     return out
 
@@ -368,7 +379,8 @@ def rbf_geom_create(ctx: int, xs, xv, dwall=None) -> int:
 
 
 def rbf_geom_volume_update(ctx: int, geom: int, radius: Sequence[float], D: Sequence[float],
-                           level_off: Sequence[int], xc, alpha, dv, precision: str = "fp64", stream=None):
+                           level_off: Sequence[int], xc, alpha, dv, precision: str = "fp64", stream=None,
+                           basis: str = "c2"):
     """Enqueue the volume update on a resident geometry (prefix of its wall-distance order);
     dv is [dim, n_v] in the geometry's original point order."""
     nl = len(radius)
@@ -387,7 +399,7 @@ def rbf_geom_volume_update(ctx: int, geom: int, radius: Sequence[float], D: Sequ
     d = (_f64 * nl)(*[float(x) for x in D])
     off = (_i32 * (nl + 1))(*[int(x) for x in level_off])
     _check(lib().rbf_geom_volume_update(ctx, geom, nl, r, d, off, ldc, pxc, pa, pdv,
-                                        RBF_MIXED if precision == "mixed" else RBF_FP64, _stream(stream)),
+                                        RBF_MIXED if precision == "mixed" else RBF_FP64, _basis(basis), _stream(stream)),
            "rbf_geom_volume_update")
     return dv
 
@@ -408,11 +420,12 @@ class Request:
 
 def rbf_submit(ctx: int, geom: int, ds, dv, radius: Sequence[float], eps: float, D: Sequence[float],
                rho: float = 0.1, cap: int = 0, seeds=None, precision: str = "mixed",
-               warm_start: bool = False, want_ctrl: bool = False, d_factor: float = 0.0) -> Request:
+               warm_start: bool = False, want_ctrl: bool = False, d_factor: float = 0.0,
+               basis: str = "c2") -> Request:
     import torch
 
     dim, n_s = ds.shape
-    p, keep = make_params(dim, radius, eps, rho, cap, seeds, precision, n_s)
+    p, keep = make_params(dim, radius, eps, rho, cap, seeds, precision, n_s, basis)
     req = rbf_request()
     req.geom = geom
     req.ds, _ = _dev(ds, "ds", dim, n_s)
