@@ -32,7 +32,17 @@ METRIC = ("RBF evals/s (volume update: reduced-volume points x control points pe
           "outside the compact support are skipped, not computed), greedy time-to-eps, p50/p99 "
           "request latency")
 VALU_LANE_OPS = 256 * 64 * 2.4e9          # 256 CUs x 64 lanes x 2.4 GHz
-MIN_SLOTS = {2: 17, 3: 20}                 # minimal VALU slots per pair (FP64), see the design doc
+# Minimal VALU issue slots per (point, control) pair with the Wendland C2 basis: dim subtractions,
+# the squared distance (dim multiply-adds), the square root (a quarter-rate op: 4 slots), 1 - eta,
+# the clamp at 0, t^2 and t^4, 4 eta + 1, the product, and dim accumulating multiply-adds; points
+# and controls are pre-scaled by 1/R. Other bases change the polynomial part; the FP32 pair form
+# adds one conversion to FP64 before the accumulation.
+MIN_SLOTS = {2: 17, 3: 20}
+BASIS_SLOTS = {"c0": -3, "c2": 0, "c4": 2, "c6": 3}
+
+
+def min_slots(dim, basis, precision):
+    return MIN_SLOTS[dim] + BASIS_SLOTS[basis] + (1 if precision == "mixed" else 0)
 
 
 def log(msg):
@@ -57,6 +67,12 @@ def build_workload(name):
     if name == "cfg3":
         return synth.workload_cfg3(), ("3D swept wing bend+twist: N_s=80000, N_v=4000000, "
                                        "R_l=3c/0.8c/0.2c, eps=1e-4c, cap 4000, D=1c")
+    if name == "sine2d":
+        return synth.workload_sine2d(), ("2D NACA0012 global deformation dy = 0.01 sin(15 pi x): N_s=4000, "
+                                         "N_v=400000, R=2c on 5 levels, eps=1e-5 max|dS|, D_l = 5 max|dS_l|")
+    if name == "sine3d":
+        return synth.workload_sine3d(), ("3D swept wing global deformation 0.03 sin(4 pi y): N_s=80000, "
+                                         "N_v=4000000, R=3c on 4 levels, eps=1e-4c, cap 4000, D_l = 5 max|dS_l|")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -81,28 +97,67 @@ def measured_traffic(workload, precision):
     return float(fields["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(w, ref, budget_s=12.0):
-    """FP64 oracle timed on the host cores: the volume update on the oracle's own control set,
-    repeated on the full reduced volume until about budget_s seconds have passed."""
+def _omp():
+    """The OpenMP runtime the oracle library uses (to read and set its thread count)."""
+    import ctypes
+
+    try:
+        return ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+
+
+def cpu_baseline(w, cs, radius, D, off, basis, big, budget_s=12.0):
+    """The FP64 oracle timed on this machine's host cores, on a bounded sample of the same
+    workload: the volume update of the step's control sets over the reduced volume (all of it,
+    or a seeded subset when one pass would be long), repeated for about budget_s seconds; the same
+    on one thread for a short while; and the oracle's whole greedy where it is affordable."""
     import numpy as np
 
     import oracle
 
     o = oracle.get()
-    D = [w.D] * w.n_levels
-    xc = np.ascontiguousarray(w.xs[:, ref.ctrl_idx])
-    counts = [int((w.dwall < D[l]).sum()) for l in range(w.n_levels)]
-    pairs = sum(counts[l] * int(ref.level_off[l + 1] - ref.level_off[l]) for l in range(w.n_levels))
-    reps, t = 0, 0.0
-    while t < budget_s and reps < 1000:
-        t0 = time.perf_counter()
-        o.volume(w.radius, D, ref.level_off, xc, ref.alpha, w.xv, w.dwall)
-        t += time.perf_counter() - t0
-        reps += 1
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": pairs * reps / t, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"full reduced volume ({counts[0]} of {w.n_v} points) x {ref.level_off[-1]} "
-                      f"oracle control points, {reps} repetitions in {t:.1f} s"}
+    xc = cs.xc[:, : cs.total].cpu().numpy()
+    al = cs.alpha[:, : cs.total].cpu().numpy()
+    inside = np.flatnonzero(w.dwall < max(D))
+    per_point = np.zeros(w.n_v)
+    for l in range(len(radius)):
+        per_point += (w.dwall < D[l]) * (off[l + 1] - off[l])
+    rng = np.random.default_rng(5)
+    n_pick = int(min(inside.size, max(1000, 2e9 / max(1.0, per_point[inside].mean()))))
+    pick = np.sort(rng.choice(inside, n_pick, replace=False)) if n_pick < inside.size else inside
+    xv, dwp = np.ascontiguousarray(w.xv[:, pick]), np.ascontiguousarray(w.dwall[pick])
+    pairs = float(per_point[pick].sum())
+    omp = _omp()
+    cores = int(omp.omp_get_max_threads()) if omp else int(os.environ.get("OMP_NUM_THREADS", 1))
+
+    def timed(fn, budget):
+        reps, t = 0, 0.0
+        while t < budget and reps < 1000:
+            t0 = time.perf_counter()
+            fn()
+            t += time.perf_counter() - t0
+            reps += 1
+        return reps, t
+
+    vol = lambda pts=xv, d=dwp: o.volume(radius, D, off, xc, al, pts, d, basis=basis)
+    reps, t = timed(vol, budget_s)
+    out = {"value": pairs * reps / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+           "sample": f"volume update of the step's {cs.total} control points over {pick.size} of the "
+                     f"{inside.size} reduced-volume points ({pairs:.3g} pairs), {reps} repetitions in "
+                     f"{t:.1f} s"}
+    if omp:
+        sub = pick[: max(1, pick.size // max(1, cores))]
+        omp.omp_set_num_threads(1)
+        r1, t1 = timed(lambda: vol(np.ascontiguousarray(w.xv[:, sub]), np.ascontiguousarray(w.dwall[sub])), 2.0)
+        omp.omp_set_num_threads(cores)
+        out["single_thread_value"] = float(per_point[sub].sum()) * r1 / t1
+    if not big:
+        g = lambda: o.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
+                             seeds=w.seeds, basis=basis)
+        rg, tg = timed(g, 3.0)
+        out["greedy_time_to_eps_s"] = tg / rg
+    return out
 
 
 def serving_replay(ctx, geoms, reqs, time_scale=1.0, compare=True):
@@ -148,7 +203,8 @@ def serving_replay(ctx, geoms, reqs, time_scale=1.0, compare=True):
     pct = lambda v, q: v[min(len(v) - 1, int(q * len(v)))]
     out = {
         "requests": len(reqs), "geometries": len(geoms), "icing_steps": steps, "failed": failed,
-        "arrival_rate_per_s": len(reqs) / (reqs[-1].arrival * time_scale) if reqs[-1].arrival > 0 else None,
+        "arrival_rate_per_s": (len(reqs) / (reqs[-1].arrival * time_scale)
+                               if reqs[-1].arrival * time_scale > 0 else None),
         "p50_latency_ms": pct(lat, 0.50), "p99_latency_ms": pct(lat, 0.99),
         "p50_queue_ms": pct(queue, 0.50), "mean_service_ms": statistics.mean(service),
         "throughput_req_per_s": len(reqs) / (t_end - t0),
@@ -177,13 +233,38 @@ def serving_replay(ctx, geoms, reqs, time_scale=1.0, compare=True):
     return out
 
 
+def _median_ms(stream, fn, reps):
+    import torch
+
+    evs = []
+    for _ in range(reps):
+        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a_.record(stream)
+        fn()
+        b_.record(stream)
+        evs.append((a_, b_))
+    torch.cuda.synchronize()
+    return statistics.median(a_.elapsed_time(b_) for a_, b_ in evs)
+
+
+def _normwise(got, ref):
+    import numpy as np
+
+    scale = np.sqrt((ref ** 2).sum(0)).max()
+    err = np.sqrt(((got - ref) ** 2).sum(0))
+    return {"max_abs": float(err.max()), "rms": float(np.sqrt((err ** 2).mean())),
+            "normwise": float(err.max() / scale) if scale > 0 else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg1")
+    ap.add_argument("--workload", default="cfg1",
+                    help="cfg0..cfg3, sine2d, sine3d (one deformation per step), or cfg4 (serving mix)")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--basis", default="c2", choices=["c0", "c2", "c4", "c6"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-geometries", type=int, default=16,
                     help="geometries of the reduced serving mix replayed after the main timing (0: skip)")
@@ -208,29 +289,38 @@ def main():
     t0 = time.perf_counter()
     w, desc = build_workload(args.workload)
     log(f"bench: workload {w.name} built in {time.perf_counter() - t0:.1f}s")
+    big = w.n_s * w.cap_total() > 5e7       # the oracle's whole greedy would take minutes
     dev = torch.device("cuda:0")
     xs = torch.from_numpy(w.xs).to(dev)
     ds = torch.from_numpy(w.ds).to(dev)
     xv = torch.from_numpy(w.xv).to(dev)
     dw = torch.from_numpy(w.dwall).to(dev)
-    D = [w.D] * w.n_levels
     ctx = rbfdef.rbf_ctx_create(0)
     stream = torch.cuda.current_stream()
     # Setup, outside the timed region: the geometry (surface, volume, wall distances) becomes
-    # resident once, its volume stored in wall-distance order, as across successive icing steps.
+    # resident once, as across successive icing steps.
     geom = rbfdef.rbf_geom_create(ctx, xs, xv, dw)
     dv = torch.empty((w.dim, w.n_v), dtype=torch.float64, device=dev)
+
+    def supports(cs):
+        """Per-level (radius, D, level_off) of a step: fixed D, or D_l = k (dS_l)^max."""
+        if w.d_factor > 0:
+            used = cs.n_levels_used
+            return w.radius[:used], cs.support_distances(w.d_factor), cs.level_off[: used + 1]
+        return w.radius, [w.D] * w.n_levels, cs.level_off
 
     def step():
         g0 = time.perf_counter()
         cs = rbfdef.rbf_greedy_select(ctx, xs, ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
-                                      seeds=w.seeds, precision=args.precision, want_residual=False)
+                                      seeds=w.seeds, precision=args.precision, want_residual=False,
+                                      basis=args.basis)
         g1 = time.perf_counter()
+        radius, D, off = supports(cs)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        rbfdef.rbf_geom_volume_update(ctx, geom, w.radius, D, cs.level_off, cs.xc, cs.alpha, dv,
-                                      precision=args.precision)
+        rbfdef.rbf_geom_volume_update(ctx, geom, radius, D, off, cs.xc, cs.alpha, dv,
+                                      precision=args.precision, basis=args.basis)
         e1.record(stream)
         return cs, g1 - g0, (e0, e1)
 
@@ -256,36 +346,85 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     vol_ms = [a.elapsed_time(b) for a, b in events]
-    k_ms, k_n = rbfdef.rbf_ctx_kernel_time(ctx, "volume_ksum_" + args.precision)
-    k_pairs = rbfdef.rbf_ctx_kernel_pairs(ctx, "volume_ksum_" + args.precision)
+    kname = "volume_ksum_" + args.precision
+    k_ms, k_n = rbfdef.rbf_ctx_kernel_time(ctx, kname)
+    rbfdef.rbf_ctx_set_timing(ctx, False)
     log(f"bench: {args.steps} steps in {wall:.3f}s")
+    radius, D, off = supports(cs)
+    vol_call = lambda prec: rbfdef.rbf_geom_volume_update(ctx, geom, radius, D, off, cs.xc, cs.alpha, dv,
+                                                          precision=prec, basis=args.basis)
+    # Pairs the kernel computes per launch: one more, untimed launch with the device counter on.
+    rbfdef.rbf_ctx_set_timing(ctx, False, count_pairs=True)
+    vol_call(args.precision)
+    evaluated = float(rbfdef.rbf_ctx_kernel_pairs(ctx, kname))
+    rbfdef.rbf_ctx_set_timing(ctx, False)
     # Secondary: the plain call on the caller's (unsorted) volume, with its per-call compaction.
-    plain = []
-    for _ in range(5):
-        a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a_.record(stream)
-        rbfdef.rbf_volume_update(ctx, w.radius, D, cs.level_off, cs.xc, cs.alpha, xv, dw,
-                                 precision=args.precision)
-        b_.record(stream)
-        plain.append((a_, b_))
-    torch.cuda.synchronize()
-    plain_ms = statistics.median(a_.elapsed_time(b_) for a_, b_ in plain)
+    plain_ms = _median_ms(stream, lambda: rbfdef.rbf_volume_update(
+        ctx, radius, D, off, cs.xc, cs.alpha, xv, dw, precision=args.precision, basis=args.basis), 5)
 
-    n_c = [cs.level_off[l + 1] - cs.level_off[l] for l in range(w.n_levels)]
-    n_d = [int((w.dwall < D[l]).sum()) for l in range(w.n_levels)]
-    pairs = sum(n_d[l] * n_c[l] for l in range(w.n_levels))
+    n_c = [off[l + 1] - off[l] for l in range(len(radius))]
+    n_d = [int((w.dwall < D[l]).sum()) for l in range(len(radius))]
+    pairs = sum(n_d[l] * n_c[l] for l in range(len(radius)))
     value = pairs * args.steps / (sum(vol_ms) / 1e3)
     avg_kernel_s = (k_ms / k_n) / 1e3 if k_n else float("nan")
-    peak = VALU_LANE_OPS / MIN_SLOTS[w.dim] / 1e9
-    evaluated = k_pairs / k_n if k_n else float("nan")     # pairs the kernel computed per launch
+    peak = VALU_LANE_OPS / min_slots(w.dim, args.basis, args.precision) / 1e9
     achieved = evaluated / avg_kernel_s / 1e9
 
-    # Parity and CPU baseline outside the timed region.
-    ref = oracle.get().greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
-                              seeds=w.seeds)
-    same = bool(np.array_equal(cs.ctrl_idx[: cs.total].cpu().numpy(), ref.ctrl_idx))
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w, ref)
+    # Precision study on this step's control sets: the FP32 pair arithmetic (shifted local origin,
+    # FP64 accumulation) beside the FP64 path, and both against the FP64 oracle on sampled points.
+    ms64 = _median_ms(stream, lambda: vol_call("fp64"), 10)
+    vol_call("fp64")
+    torch.cuda.synchronize()
+    dv64 = dv.cpu().numpy()
+    msmx = _median_ms(stream, lambda: vol_call("mixed"), 10)
+    vol_call("mixed")
+    torch.cuda.synchronize()
+    dvmx = dv.cpu().numpy()
+    # The guarded form: FP32 only on the levels whose measured FP32 error at the surface is at
+    # most 1e-6 max |dS| (what a mixed-precision request runs). The step's greedy ran in FP64
+    # unless --precision mixed, so the measurement comes from one mixed greedy here.
+    csm = cs if args.precision == "mixed" else rbfdef.rbf_greedy_select(
+        ctx, xs, ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds, precision="mixed",
+        want_residual=False, basis=args.basis)
+    guard = ["mixed" if f else "fp64" for f in csm.fp32_levels()][: len(radius)]
+    msg = _median_ms(stream, lambda: vol_call(guard), 10)
+    vol_call(guard)
+    torch.cuda.synchronize()
+    dvg = dv.cpu().numpy()
+    inside = np.flatnonzero(w.dwall < max(D))
+    pick = np.random.default_rng(11).choice(inside, min(20000, inside.size), replace=False)
+    xcn = cs.xc[:, : cs.total].cpu().numpy()
+    aln = cs.alpha[:, : cs.total].cpu().numpy()
+    orc = oracle.get()
+    ref_s = orc.volume(radius, D, off, xcn, aln, w.xv[:, pick], w.dwall[pick], basis=args.basis)
+    study = {"fp64_volume_update_ms": ms64, "mixed_volume_update_ms": msmx,
+             "mixed_speedup": ms64 / msmx,
+             "mixed_vs_fp64_gpu": _normwise(dvmx, dv64),
+             "fp64_vs_oracle_sampled": _normwise(dv64[:, pick], ref_s),
+             "mixed_vs_oracle_sampled": _normwise(dvmx[:, pick], ref_s),
+             "level_fp32_err_at_surface": csm.level_fp32_err[: csm.n_levels_used],
+             "guarded_levels": guard,
+             "guarded_volume_update_ms": msg,
+             "guarded_vs_fp64_gpu": _normwise(dvg, dv64),
+             "guarded_vs_oracle_sampled": _normwise(dvg[:, pick], ref_s),
+             "oracle_sample_points": int(pick.size)}
 
+    # Selection parity outside the timed region: the whole greedy where the oracle affords it,
+    # otherwise its first 60 selections (the argmax sequence does not depend on the cap).
+    if big:
+        k = 60
+        ref = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=k, seeds=w.seeds,
+                         basis=args.basis)
+        same = bool(np.array_equal(cs.ctrl_idx[:k].cpu().numpy(), ref.ctrl_idx[:k]))
+        parity = f"first {k} selections against the oracle's greedy capped at {k}"
+    else:
+        ref = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
+                         seeds=w.seeds, basis=args.basis)
+        same = bool(np.array_equal(cs.ctrl_idx[: cs.total].cpu().numpy(), ref.ctrl_idx))
+        parity = "whole control set against the oracle's greedy"
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w, cs, radius, D, off, args.basis, big)
+
+    used = cs.n_levels_used
     rec = {
         "metric": METRIC,
         "value": value,
@@ -299,23 +438,33 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {desc}", "precision": args.precision,
-                   "control_points_per_level": n_c, "reduced_volume_points_per_level": n_d,
+        "config": {"workload": f"{w.name}: {desc}", "precision": args.precision, "basis": args.basis,
+                   "control_points_per_level": n_c, "support_distance_per_level": D,
+                   "reduced_volume_points_per_level": n_d,
                    "pairs_per_volume_update": pairs,
                    "evaluated_pairs_per_volume_update": evaluated,
                    "parallelism": "single GPU"},
         "greedy_time_to_eps_s": statistics.median(greedy_t),
         "greedy_iterations": cs.n_iterations,
+        "greedy_iterations_per_s": cs.n_iterations / statistics.median(greedy_t),
+        "greedy_levels": [{"controls": n_c[l] if l < len(n_c) else 0, "seconds": cs.level_seconds[l],
+                           "max_err_in": cs.level_in_max[l], "max_err_out": cs.level_max_err[l]}
+                          for l in range(used)],
         "volume_update_ms": statistics.median(vol_ms),
         "plain_volume_update_ms": plain_ms,
         "plain_volume_update_evals_per_s": pairs / (plain_ms / 1e3),
         "selection_identical_to_oracle": same,
+        "selection_check": parity,
+        "precision_study": study,
         "p50_latency_ms": None,
         "p99_latency_ms": None,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(args.workload, args.precision),
-                     "kernel": "volume_ksum_" + args.precision,
-                     "kernel_avg_ms": avg_kernel_s * 1e3, "kernel_launches": k_n},
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic(args.workload, args.precision)
+                     if args.basis == "c2" else None,
+                     "kernel": kname, "kernel_avg_ms": avg_kernel_s * 1e3, "kernel_launches": k_n,
+                     "work_unit": "evaluated (point, control) pairs per launch, "
+                                  "controls whose support misses a point block skipped"},
         "cpu_baseline": cpu,
     }
     rbfdef.rbf_geom_release(ctx, geom)
@@ -327,6 +476,11 @@ def main():
         srv = serving_replay(ctx, geoms, reqs)
         srv["mix"] = (f"{args.serve_geometries} geometries at size scale {args.serve_scale} of the "
                       "serving mix, 4 icing steps each, Poisson arrivals at 20/s, mixed precision")
+        sat = serving_replay(ctx, geoms, reqs, time_scale=0.0, compare=False)
+        srv["saturated"] = {"throughput_req_per_s": sat["throughput_req_per_s"],
+                            "p50_latency_ms": sat["p50_latency_ms"], "p99_latency_ms": sat["p99_latency_ms"],
+                            "makespan_s": sat["makespan_s"],
+                            "note": "every request submitted at t = 0 (capacity of the serving loop)"}
         rec["p50_latency_ms"] = srv["p50_latency_ms"]
         rec["p99_latency_ms"] = srv["p99_latency_ms"]
         rec["serving"] = srv

@@ -45,7 +45,11 @@ typedef int32_t rbf_status;
 
 #define RBF_FP64 0   /* every kernel sum in FP64 */
 #define RBF_MIXED 1  /* volume kernel sums in FP32 on locally shifted coordinates with an FP64
-                        accumulator; greedy factor, convergence check and residuals stay FP64 */
+                        accumulator; greedy factor, convergence check and residuals stay FP64.
+                        The greedy measures each level's FP32 error at the surface
+                        (level_fp32_err), and a request runs a level's volume sums in FP32 only
+                        when that error is at most RBF_MIXED_TOL max_i ||dS_i|| (FP64 otherwise) */
+#define RBF_MIXED_TOL 1e-6
 
 /* Basis functions phi(eta), eta = ||r - r_c|| / R, the Wendland functions of Table 1, each zero
  * for eta >= 1 and 1 at eta = 0. C2 (eq. (2)) is the paper's choice and the zero default. */
@@ -79,11 +83,13 @@ const char *rbf_last_error(void);
 /* Library-owned device bytes currently held by the context (pool high-water included). */
 uint64_t rbf_ctx_bytes_in_use(rbf_ctx ctx);
 
-/* Kernel timing for measurement: when enabled, the main kernel-sum launch of every call is
+/* Kernel timing for measurement. flags bit 0: the main kernel-sum launch of every call is
  * bracketed by a pair of hipEvents on its stream (adds two event records per launch). Kernel
  * names: "volume_ksum_fp64", "volume_ksum_mixed", "surface_ksum_fp64", "surface_ksum_mixed".
  * rbf_ctx_kernel_time waits for the recorded events and returns the summed device time (ms)
- * and the number of launches since timing was last enabled; set_timing clears the totals. */
+ * and the number of launches since timing was last enabled; set_timing clears the totals.
+ * flags bit 1: every workgroup of those launches also adds the pairs it evaluated to a device
+ * counter (one atomic per workgroup, so time with bit 0 alone). */
 rbf_status rbf_ctx_set_timing(rbf_ctx ctx, int32_t enabled);
 rbf_status rbf_ctx_kernel_time(rbf_ctx ctx, const char *kernel, double *total_ms, int64_t *launches);
 /* (point, control) pairs the named kernel sums actually evaluated since timing was last enabled:
@@ -128,6 +134,9 @@ typedef struct {
                                               (dS_l)^max of the support distance D_l = k (dS_l)^max
                                               (section 4); 0 for levels not run */
     double level_seconds[RBF_MAX_LEVELS];  /* out: host wall time of each level (timing only) */
+    double level_fp32_err[RBF_MAX_LEVELS]; /* out, with RBF_MIXED: max_i ||s_l32(x_i) - s_l(x_i)||
+                                              over the surface, the error of level l's interpolant
+                                              with FP32 pair arithmetic against FP64; 0 otherwise */
     int64_t n_iterations;                  /* out: argmax selections made (seeds excluded) */
 } rbf_ctrl_set;
 
@@ -156,13 +165,14 @@ rbf_status rbf_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_
  * and are skipped (the volume point reduction of Section 4).
  * radius, D: host [n_levels]; level_off: host [n_levels + 1] offsets into xc/alpha;
  * xc, alpha: device [dim][ld_ctrl]; xv: device [dim][n_v]; dwall: device [n_v];
- * dv: device [dim][n_v] output (fully written). precision: RBF_FP64 or RBF_MIXED; basis:
- * RBF_WENDLAND_*. Enqueued on `stream`; returns before the device work finishes. */
+ * dv: device [dim][n_v] output (fully written). precision: RBF_FP64 or RBF_MIXED for every
+ * level, or level_precision (host [n_levels], nullable) per level; basis: RBF_WENDLAND_*.
+ * Enqueued on `stream`; returns before the device work finishes. */
 rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
                              const double *D, const int32_t *level_off, int64_t ld_ctrl,
                              const double *xc, const double *alpha, int64_t n_v, const double *xv,
-                             const double *dwall, double *dv, int32_t precision, int32_t basis,
-                             void *stream);
+                             const double *dwall, double *dv, int32_t precision,
+                             const int32_t *level_precision, int32_t basis, void *stream);
 
 /* Interpolant evaluation, eq. (1) with the support of eq. (2), at n_p points:
  *   out_k(p) = base_k(p) - sign * sum_c phi(||x_p - xc_c|| / radius) alpha_k,c
@@ -226,7 +236,8 @@ typedef struct {
 rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, const double *radius,
                                   const double *D, const int32_t *level_off, int64_t ld_ctrl,
                                   const double *xc, const double *alpha, double *dv,
-                                  int32_t precision, int32_t basis, void *stream);
+                                  int32_t precision, const int32_t *level_precision, int32_t basis,
+                                  void *stream);
 
 /* Non-blocking. RBF_E_NOMEM if the request could never fit the budget. */
 rbf_status rbf_submit(rbf_ctx ctx, const rbf_request *req, rbf_ticket *out);

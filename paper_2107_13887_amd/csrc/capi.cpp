@@ -174,7 +174,7 @@ void KernelTimers::end(const char *name, hipEvent_t a, hipStream_t s)
 unsigned long long *KernelTimers::counter(const char *name)
 {
     std::lock_guard<std::mutex> lk(mu);
-    if (!enabled || !dev_count) return nullptr;
+    if (!count_pairs || !dev_count) return nullptr;
     auto it = slot.find(name);
     if (it == slot.end()) {
         if ((int)slot.size() >= N_COUNT) return nullptr;
@@ -206,6 +206,16 @@ void KernelTimers::resolve()
 }
 
 // ---- validation -------------------------------------------------------------------------------
+rbf_status check_precision(int32_t precision, const int32_t *level_precision, int32_t n_levels)
+{
+    if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_E_INVALID, "bad precision %d", precision);
+    if (level_precision)
+        for (int l = 0; l < n_levels; ++l)
+            if (level_precision[l] != RBF_FP64 && level_precision[l] != RBF_MIXED)
+                return fail(RBF_E_INVALID, "bad level_precision[%d] = %d", l, level_precision[l]);
+    return RBF_OK;
+}
+
 rbf_status validate_params(const rbf_greedy_params &p, int64_t n_s)
 {
     if (p.dim != 2 && p.dim != 3) return fail(RBF_E_INVALID, "dim must be 2 or 3 (got %d)", p.dim);
@@ -312,9 +322,10 @@ rbf_status rbf_ctx_set_timing(rbf_ctx ctx, int32_t enabled)
     ctx->timers.resolve();
     RBF_HIP(hipSetDevice(ctx->device));
     std::lock_guard<std::mutex> lk(ctx->timers.mu);
-    ctx->timers.enabled = enabled != 0;
+    ctx->timers.enabled = (enabled & 1) != 0;
+    ctx->timers.count_pairs = (enabled & 2) != 0;
     ctx->timers.total.clear();
-    if (enabled && !ctx->timers.dev_count)
+    if (ctx->timers.count_pairs && !ctx->timers.dev_count)
         RBF_HIP(hipMalloc((void **)&ctx->timers.dev_count, sizeof(unsigned long long) * KernelTimers::N_COUNT));
     if (ctx->timers.dev_count) {
         RBF_HIP(hipDeviceSynchronize());
@@ -397,15 +408,15 @@ static rbf_status check_levels(int32_t n_levels, const double *radius, const dou
 rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
                              const double *D, const int32_t *level_off, int64_t ld_ctrl,
                              const double *xc, const double *alpha, int64_t n_v, const double *xv,
-                             const double *dwall, double *dv, int32_t precision, int32_t basis,
-                             void *stream)
+                             const double *dwall, double *dv, int32_t precision,
+                             const int32_t *level_precision, int32_t basis, void *stream)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
     if (dim != 2 && dim != 3) return fail(RBF_E_INVALID, "dim must be 2 or 3");
     if (!D) return fail(RBF_E_INVALID, "D is NULL");
     RBF_TRY(check_levels(n_levels, radius, D, level_off, ld_ctrl));
     if (n_v < 0 || n_v > (int64_t(1) << 31) - 1) return fail(RBF_E_INVALID, "n_v out of range");
-    if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_E_INVALID, "bad precision");
+    RBF_TRY(check_precision(precision, level_precision, n_levels));
     if (!basis_valid(basis)) return fail(RBF_E_INVALID, "unknown basis %d", basis);
     if (n_v == 0) return RBF_OK;
     if (!xv || !dwall || !dv || (level_off[n_levels] > level_off[0] && (!xc || !alpha)))
@@ -415,7 +426,8 @@ rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const d
     pb.dim = dim;
     pb.n_levels = n_levels;
     for (int l = 0; l < n_levels; ++l)
-        pb.lv[l] = SumLevel{1.0 / radius[l], D[l], level_off[l], level_off[l + 1]};
+        pb.lv[l] = SumLevel{1.0 / radius[l], D[l], level_off[l], level_off[l + 1],
+                            (level_precision ? level_precision[l] : precision) == RBF_MIXED};
     pb.ld_ctrl = ld_ctrl;
     pb.xc = xc;
     pb.alpha = alpha;
@@ -448,7 +460,7 @@ rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, in
     SumProblem pb;
     pb.dim = dim;
     pb.n_levels = 1;
-    pb.lv[0] = SumLevel{1.0 / radius, 0.0, 0, n_c};
+    pb.lv[0] = SumLevel{1.0 / radius, 0.0, 0, n_c, precision == RBF_MIXED};
     pb.ld_ctrl = ld_ctrl;
     pb.xc = xc;
     pb.alpha = alpha;

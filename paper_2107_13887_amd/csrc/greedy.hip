@@ -65,7 +65,8 @@ struct GArgs {
     int64_t n_s;
     double R;
     int32_t basis;       // RBF_WENDLAND_*
-    double *V;           // [cols][n_s] column-major Newton basis
+    double *V;           // Newton basis, tile-major: V(i, j) at ((i / UPB) ldt + j) UPB + i % UPB
+    int64_t ldt;         // columns per tile in V
     double *Lpack;       // packed lower factor, row n at n (n + 1) / 2
     double *coef;        // [DIM][ld_coef] Newton coefficients y
     int64_t ld_coef;
@@ -250,7 +251,7 @@ __device__ void select_phase(const GArgs &a, int64_t forced, SelShared &s)
     double *row = a.Lpack + (n * (n + 1)) / 2;
     double part_ll = 0.0;
     for (int64_t j = threadIdx.x; j < n; j += NT) {
-        const double v = a.V[j * a.n_s + p];
+        const double v = a.V[((p / UPB) * a.ldt + j) * UPB + (p % UPB)];
         row[j] = v;
         part_ll = __builtin_fma(v, v, part_ll);
     }
@@ -298,8 +299,7 @@ __device__ void update_tile(const GArgs &a, int64_t tile, int64_t n, int64_t p, 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = tile * UPB + lane;
     const bool ok = i < a.n_s;
-    const int64_t ic = ok ? i : 0;
-    const int64_t ldV = a.n_s;
+    const double *vt = a.V + tile * a.ldt * UPB + lane;   // this tile's columns, 512 B each
 
     double s = 0.0;
     for (int64_t j0 = 0; j0 < n; j0 += LCHUNK) {
@@ -309,16 +309,30 @@ __device__ void update_tile(const GArgs &a, int64_t tile, int64_t n, int64_t p, 
         __syncthreads();
         const int per = (nj + UWAVES - 1) / UWAVES;
         const int jb = w * per, je = min(nj, jb + per);
-        const double *col = a.V + (j0 + jb) * ldV + ic;
+        const double *col = vt + (j0 + jb) * UPB;
         int j = jb;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (; j + 4 <= je; j += 4, col += 4 * ldV) {
-            s0 = __builtin_fma(col[0], u.lsh[j], s0);
-            s1 = __builtin_fma(col[ldV], u.lsh[j + 1], s1);
-            s2 = __builtin_fma(col[2 * ldV], u.lsh[j + 2], s2);
-            s3 = __builtin_fma(col[3 * ldV], u.lsh[j + 3], s3);
+        // Sixteen column loads in flight per lane before any is consumed: the loop is bound by
+        // memory, not by the multiply-adds.
+        for (; j + 16 <= je; j += 16, col += 16 * UPB) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = col[q * UPB];
+#pragma unroll
+            for (int q = 0; q < 16; q += 4) {
+                s0 = __builtin_fma(v[q], u.lsh[j + q], s0);
+                s1 = __builtin_fma(v[q + 1], u.lsh[j + q + 1], s1);
+                s2 = __builtin_fma(v[q + 2], u.lsh[j + q + 2], s2);
+                s3 = __builtin_fma(v[q + 3], u.lsh[j + q + 3], s3);
+            }
         }
-        for (; j < je; ++j, col += ldV) s0 = __builtin_fma(col[0], u.lsh[j], s0);
+        for (; j + 4 <= je; j += 4, col += 4 * UPB) {
+            s0 = __builtin_fma(col[0], u.lsh[j], s0);
+            s1 = __builtin_fma(col[UPB], u.lsh[j + 1], s1);
+            s2 = __builtin_fma(col[2 * UPB], u.lsh[j + 2], s2);
+            s3 = __builtin_fma(col[3 * UPB], u.lsh[j + 3], s3);
+        }
+        for (; j < je; ++j, col += UPB) s0 = __builtin_fma(col[0], u.lsh[j], s0);
         s += (s0 + s1) + (s2 + s3);
     }
     u.psum[w][lane] = s;
@@ -331,7 +345,7 @@ __device__ void update_tile(const GArgs &a, int64_t tile, int64_t n, int64_t p, 
 #pragma unroll
             for (int k = 1; k < UWAVES; ++k) dot += u.psum[k][lane];
             const double v = (phi_pair<DIM>(a.xs, a.n_s, i, p, a.R, a.basis) - dot) / d;
-            a.V[n * ldV + i] = v;
+            a.V[(tile * a.ldt + n) * UPB + lane] = v;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) a.E[k * a.n_s + i] = __builtin_fma(-c[k], v, a.E[k * a.n_s + i]);
             if (!a.sel[i]) {
@@ -620,7 +634,6 @@ __global__ __launch_bounds__(NT) void g_apply(GArgs a, const double *r, int64_t 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * UPB + lane;
     const bool ok = i < a.n_s;
-    const int64_t ic = ok ? i : 0;
     double s[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) s[k] = 0.0;
@@ -635,7 +648,7 @@ __global__ __launch_bounds__(NT) void g_apply(GArgs a, const double *r, int64_t 
         const int per = (nj + UWAVES - 1) / UWAVES;
         const int jb = w * per, je = min(nj, jb + per);
         for (int j = jb; j < je; ++j) {
-            const double v = a.V[(j0 + j) * a.n_s + ic];
+            const double v = a.V[((int64_t)blockIdx.x * a.ldt + j0 + j) * UPB + lane];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) s[k] = __builtin_fma(v, ysh[k][j], s[k]);
         }
@@ -670,6 +683,30 @@ __global__ void g_set_count(GState *st, int64_t n)
         st->go = 0;
         st->stop = -1;
     }
+}
+
+// Per-workgroup maximum over its points of ||(r - r_next) - t||: the difference between the
+// level's FP64 interpolant (r - r_next) and another evaluation t of it, at the surface points.
+template <int DIM>
+__global__ __launch_bounds__(256) void g_maxdiff(const double *r, const double *r_next, const double *t,
+                                                 int64_t n_s, double *part)
+{
+    __shared__ double red[256];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double e2 = 0.0;
+    if (i < n_s)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const double d = (r[k * n_s + i] - r_next[k * n_s + i]) - t[k * n_s + i];
+            e2 = __builtin_fma(d, d, e2);
+        }
+    red[threadIdx.x] = e2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
 template <int DIM>
@@ -732,7 +769,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     const int64_t g = (n_s + UPB - 1) / UPB;
 
     DevBuf bV, bL, bE, bR, bR2, bSel, bPart, bState, bCoef, bHist, bFlag, bSeeds;
-    RBF_TRY(bV.get(pool, sizeof(double) * (size_t)cols * (size_t)n_s));
+    RBF_TRY(bV.get(pool, sizeof(double) * (size_t)cols * (size_t)((n_s + UPB - 1) / UPB) * UPB));
     RBF_TRY(bL.get(pool, sizeof(double) * (size_t)(cols * (cols + 1) / 2 + 1)));
     RBF_TRY(bE.get(pool, sizeof(double) * DIM * (size_t)n_s));
     RBF_TRY(bR.get(pool, sizeof(double) * DIM * (size_t)n_s));
@@ -789,6 +826,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     a.n_s = n_s;
     a.basis = prm.basis;
     a.V = bV.as<double>();
+    a.ldt = cols;
     a.Lpack = bL.as<double>();
     a.coef = bCoef.as<double>();
     a.ld_coef = cols;
@@ -808,6 +846,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         out->level_max_err[l] = 0.0;
         out->level_in_max[l] = 0.0;
         out->level_seconds[l] = 0.0;
+        out->level_fp32_err[l] = 0.0;
     }
     for (int l = 0; l < prm.n_levels; ++l) {
         const double t_level = now_seconds();
@@ -831,7 +870,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
                               n0 <= a.cap_level &&
                               std::equal(lc.ctrl.begin(), lc.ctrl.end(), seeds_h.begin() + seed_off[l]);
             if (same) {
-                RBF_HIP(hipMemcpyAsync(a.V, lc.V.ptr, sizeof(double) * n0 * n_s, hipMemcpyDeviceToDevice, s));
+                RBF_HIP(hipMemcpy2DAsync(a.V, sizeof(double) * cols * UPB, lc.V.ptr, sizeof(double) * n0 * UPB,
+                                         sizeof(double) * n0 * UPB, g, hipMemcpyDeviceToDevice, s));
                 RBF_HIP(hipMemcpyAsync(a.Lpack, lc.L.ptr, sizeof(double) * (n0 * (n0 + 1) / 2),
                                        hipMemcpyDeviceToDevice, s));
                 RBF_HIP(hipMemcpyAsync(a.ctrl, lc.ctrl.data(), sizeof(int64_t) * n0, hipMemcpyHostToDevice, s));
@@ -934,6 +974,27 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
             pb.precision = RBF_FP64;
             pb.basis = prm.basis;
             RBF_TRY(run_kernel_sum(ctx, pb, s));
+            if (prm.precision == RBF_MIXED) {
+                // The level's interpolant with FP32 pair arithmetic, against the FP64 one: the
+                // measured error that decides whether its volume sums may run in FP32.
+                const int64_t nb = (n_s + 255) / 256;
+                DevBuf bT, bPart;
+                RBF_TRY(bT.get(pool, sizeof(double) * DIM * n_s));
+                RBF_TRY(bPart.get(pool, sizeof(double) * nb));
+                SumProblem pf = pb;
+                pf.lv[0].fp32 = 1;
+                pf.base = nullptr;
+                pf.sign = -1.0;
+                pf.out = bT.as<double>();
+                RBF_TRY(run_kernel_sum(ctx, pf, s));
+                hipLaunchKernelGGL(g_maxdiff<DIM>, dim3((unsigned)nb), dim3(256), 0, s, (const double *)R,
+                                   (const double *)R2, bT.as<const double>(), n_s, bPart.as<double>());
+                RBF_HIP(hipGetLastError());
+                std::vector<double> ph(nb);
+                RBF_HIP(hipMemcpyAsync(ph.data(), bPart.ptr, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
+                RBF_HIP(hipStreamSynchronize(s));
+                out->level_fp32_err[l] = std::sqrt(*std::max_element(ph.begin(), ph.end()));
+            }
             std::swap(R, R2);
         }
         if (store) {
@@ -942,9 +1003,10 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
             lc.V.release_after(s);
             lc.L.release_after(s);
             lc.n = 0;
-            if (n > 0 && lc.V.get(pool, sizeof(double) * n * n_s) == RBF_OK &&
+            if (n > 0 && lc.V.get(pool, sizeof(double) * n * g * UPB) == RBF_OK &&
                 lc.L.get(pool, sizeof(double) * (n * (n + 1) / 2)) == RBF_OK) {
-                RBF_HIP(hipMemcpyAsync(lc.V.ptr, a.V, sizeof(double) * n * n_s, hipMemcpyDeviceToDevice, s));
+                RBF_HIP(hipMemcpy2DAsync(lc.V.ptr, sizeof(double) * n * UPB, a.V, sizeof(double) * cols * UPB,
+                                         sizeof(double) * n * UPB, g, hipMemcpyDeviceToDevice, s));
                 RBF_HIP(hipMemcpyAsync(lc.L.ptr, a.Lpack, sizeof(double) * (n * (n + 1) / 2),
                                        hipMemcpyDeviceToDevice, s));
                 lc.ctrl.resize(n);
@@ -1000,9 +1062,10 @@ rbf_status run_greedy(rbf_ctx ctx, const rbf_greedy_params &p, int64_t n_s, cons
 
 uint64_t cache_bytes(const std::vector<LevelCache> &levels, int64_t n_s)
 {
+    const uint64_t rows = (uint64_t)((n_s + UPB - 1) / UPB) * UPB;   // V keeps whole tiles
     uint64_t b = 0;
     for (const LevelCache &lc : levels)
-        if (lc.n > 0) b += sizeof(double) * ((uint64_t)lc.n * n_s + (uint64_t)(lc.n * (lc.n + 1) / 2));
+        if (lc.n > 0) b += sizeof(double) * ((uint64_t)lc.n * rows + (uint64_t)(lc.n * (lc.n + 1) / 2));
     return b;
 }
 

@@ -92,7 +92,8 @@ struct DevBuf {
 class Server;   // serving loop (serve.cpp)
 
 // Newton basis and Cholesky factor of one greedy level, kept between requests on a geometry:
-// V is [n][n_s] (column j = basis function j at every surface point), L is packed lower
+// V holds column j (basis function j at every surface point) tile by tile: for each tile of 64
+// surface points, its n columns of 64 values are contiguous (pitch n). L is packed lower
 // (row j at j (j + 1) / 2). They depend on the geometry, the radius and the control points only,
 // so the next icing step warm-started from the same control points reuses them as they are.
 struct LevelCache {
@@ -128,6 +129,7 @@ namespace rbf {
 struct KernelTimers {
     std::mutex mu;
     bool enabled = false;
+    bool count_pairs = false;
     struct Pending { std::string name; hipEvent_t a, b; };
     std::vector<Pending> pending;
     std::map<std::string, std::pair<double, int64_t>> total;   // name -> (ms, launches)
@@ -171,6 +173,7 @@ struct SumLevel {
     double D;         // wall-distance support D_l, or 0 when psi is not applied
     int64_t c_begin;  // range in the packed control array
     int64_t c_end;
+    int32_t fp32 = 0; // 1: this level's pair arithmetic in FP32 on shifted coordinates
 };
 
 struct SumProblem {
@@ -219,6 +222,7 @@ rbf_status run_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_
 
 // ---- validation helpers (capi.cpp) ---------------------------------------------------------------
 rbf_status validate_params(const rbf_greedy_params &p, int64_t n_s);
+rbf_status check_precision(int32_t precision, const int32_t *level_precision, int32_t n_levels);
 double now_seconds();
 
 // ---- serving (serve.cpp) --------------------------------------------------------------------------

@@ -5,7 +5,8 @@
 //
 // Design (VALU-bound: about 22 vector slots per point/control pair in 2D, 25 in 3D, against 40-56
 // bytes of HBM traffic per point):
-//   * points stream as SoA, P points per lane, 256 lanes per workgroup;
+//   * points stream as SoA, P points per lane, 256 lanes per workgroup, each wave on 64 P
+//     consecutive stored points;
 //   * the controls of each level are staged through LDS in tiles of 256, scaled by 1/R_l while
 //     they are loaded (coalesced over the control index); every lane of a wave then reads the
 //     same LDS address, a broadcast without bank conflicts;
@@ -53,7 +54,6 @@ struct KArgs {
     int64_t ld_out;
     double *partial;                // [n_split][DIM][ld_part]
     int64_t ld_part;
-    double dmax;                    // max_l D_l (points at or beyond it take no part in any level)
     unsigned long long *pairs;      // evaluated (point, control) pairs are added here, or null
 };
 
@@ -124,15 +124,15 @@ __device__ __forceinline__ float pair_f32(const float (&q)[DIM], const float *c)
 template <int DIM, int P, bool MIXED, int BASIS>
 __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
 {
-    // FP64: per control DIM scaled coordinates then DIM weights. Mixed: 4 floats of shifted
-    // scaled coordinates (two doubles' room), then DIM weights in FP64.
-    constexpr int ST = MIXED ? (2 + DIM) : 2 * DIM;     // doubles per control in LDS
-    constexpr int AOFF = MIXED ? 2 : DIM;               // offset of the weights
+    // Per control in LDS: DIM scaled coordinates (FP64, or FP32 shifted ones in the first DIM
+    // floats on FP32 levels) then DIM weights in FP64.
+    constexpr int ST = 2 * DIM;                         // doubles per control in LDS
+    constexpr int AOFF = DIM;                           // offset of the weights
     constexpr int NW = BLOCK / 64;                      // waves per workgroup
     __shared__ double tile[TILE * ST];
     __shared__ double origin[DIM];
     __shared__ double wbox[NW][2 * DIM];
-    __shared__ double box[2 * DIM];                     // workgroup box: min[DIM], max[DIM]
+    __shared__ double box[2 * DIM];                     // the level's box: min[DIM], max[DIM]
     __shared__ int wcnt[NW];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n_work = a.n_work_dev ? *a.n_work_dev : a.n_work;
@@ -142,75 +142,88 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
 
     int64_t idx[P];
     bool ok[P];
-    double dw[P], acc[P][DIM], xq[P][DIM];
-    double lo[DIM], hi[DIM];
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        lo[k] = HUGE_VAL;
-        hi[k] = -HUGE_VAL;
-    }
-    // Every load of the point data is issued up front; the coordinates stay in registers.
+    double dw[P], acc[P][DIM];
+    // Point rows: wave v takes the 64 P consecutive rows from wbase + 64 P v, lane-contiguous
+    // for each p, so a wave holds neighbouring points of the stored order.
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int64_t w = wbase + p * BLOCK + tid;
+        const int64_t w = wbase + (int64_t)wave * (64 * P) + p * 64 + lane;
         ok[p] = w < n_work;
         idx[p] = ok[p] ? (a.work ? (int64_t)a.work[w] : w) : 0;
         dw[p] = (a.dwall && ok[p]) ? a.dwall[idx[p]] : 0.0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            xq[p][k] = a.xp[k * a.ld_p + idx[p]];
-            acc[p][k] = 0.0;
-        }
+        for (int k = 0; k < DIM; ++k) acc[p][k] = 0.0;
     }
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        // Box of the points some level weights (psi > 0 needs d < max_l D_l).
-        if (ok[p] && (!a.dwall || dw[p] < a.dmax)) {
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                lo[k] = fmin(lo[k], xq[p][k]);
-                hi[k] = fmax(hi[k], xq[p][k]);
-            }
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
-            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
-        }
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) {
-            wbox[wave][k] = lo[k];
-            wbox[wave][DIM + k] = hi[k];
-        }
     if (MIXED && tid == 0) {
         const int64_t i0 = a.work ? (int64_t)a.work[wbase] : wbase;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) origin[k] = a.xp[k * a.ld_p + i0];
     }
-    __syncthreads();
-    if (tid < 2 * DIM) {
-        double v = wbox[0][tid];
+    int wave_pts = 0;                                   // valid points of this wave
 #pragma unroll
-        for (int w = 1; w < NW; ++w) v = tid < DIM ? fmin(v, wbox[w][tid]) : fmax(v, wbox[w][tid]);
-        box[tid] = v;
-    }
-    __syncthreads();
-    const int64_t n_valid = min<int64_t>(BLOCK * P, n_work - wbase);
-    unsigned long long n_eval = 0;
+    for (int p = 0; p < P; ++p) wave_pts += __popcll(__ballot(ok[p]));
+    unsigned long long n_eval = 0;                      // pairs this wave evaluated
 
+    double box_d = -1.0;                                // support distance the box was built for
+    bool wave_need = false;
     for (int l = 0; l < a.n_levels; ++l) {
-        double wg[P];
-        int any = 0;
+        // The coordinates are read again for every level (cache hits) rather than held in
+        // registers across levels.
+        double wg[P], xq[P][DIM];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
             wg[p] = a.dwall ? psi_w(dw[p], a.lv[l].D) : 1.0;
-            any |= (ok[p] && wg[p] > 0.0);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) xq[p][k] = a.xp[k * a.ld_p + idx[p]];
         }
-        if (!__syncthreads_or(any)) continue;
+        // Box of the points this level weights (psi > 0), rebuilt when the support distance
+        // changes (every level shares it when D is fixed).
+        const double dl = a.dwall ? a.lv[l].D : 0.0;
+        if (l == 0 || dl != box_d) {
+            box_d = dl;
+            double lo[DIM], hi[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                lo[k] = HUGE_VAL;
+                hi[k] = -HUGE_VAL;
+            }
+            bool need = false;
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (ok[p] && wg[p] > 0.0) {
+                    need = true;
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) {
+                        lo[k] = fmin(lo[k], xq[p][k]);
+                        hi[k] = fmax(hi[k], xq[p][k]);
+                    }
+                }
+            wave_need = __ballot(need) != 0ull;          // the same in every lane of the wave
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
+                    hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
+                }
+            __syncthreads();                            // earlier readers of box are done
+            if (lane == 0)
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    wbox[wave][k] = lo[k];
+                    wbox[wave][DIM + k] = hi[k];
+                }
+            __syncthreads();
+            if (tid < 2 * DIM) {
+                double v = wbox[0][tid];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) v = tid < DIM ? fmin(v, wbox[w][tid]) : fmax(v, wbox[w][tid]);
+                box[tid] = v;
+            }
+            __syncthreads();
+        }
+        if (!(box[0] <= box[DIM])) continue;            // no point of the workgroup needs the level
+        const bool f32 = MIXED && a.lv[l].fp32;
         const double inv_r = a.lv[l].inv_r;
         int64_t cb, ce;
         split_range(a.lv[l], split, a.n_split, cb, ce);
@@ -221,8 +234,8 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                if (MIXED) q32[p][k] = (float)((xq[p][k] - origin[k]) * inv_r);
-                else q64[p][k] = xq[p][k] * inv_r;
+                q32[p][k] = (float)((xq[p][k] - (MIXED ? origin[k] : 0.0)) * inv_r);
+                q64[p][k] = xq[p][k] * inv_r;
                 la[p][k] = 0.0;
             }
         for (int64_t t0 = cb; t0 < ce; t0 += TILE) {
@@ -261,34 +274,43 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                 double *dst = tile + pos * ST;
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
-                    if (MIXED) reinterpret_cast<float *>(dst)[k] = (float)((xck[k] - origin[k]) * inv_r);
+                    if (f32) reinterpret_cast<float *>(dst)[k] = (float)((xck[k] - origin[k]) * inv_r);
                     else dst[k] = xck[k] * inv_r;
                 }
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) dst[AOFF + k] = ack[k];
             }
             __syncthreads();
-            n_eval += (unsigned long long)kept;
+            if (!wave_need) continue;                   // no point of this wave needs the level
+            n_eval += (unsigned long long)kept * (unsigned long long)wave_pts;
+            if (f32) {
 #pragma unroll 2
-            for (int c = 0; c < kept; ++c) {
-                const double *cc = tile + c * ST;
-                double cal[DIM];
-#pragma unroll
-                for (int k = 0; k < DIM; ++k) cal[k] = cc[AOFF + k];
-                if (MIXED) {
+                for (int c = 0; c < kept; ++c) {
+                    const double *cc = tile + c * ST;
+                    double cal[DIM];
                     float cpos[DIM];
 #pragma unroll
-                    for (int k = 0; k < DIM; ++k) cpos[k] = reinterpret_cast<const float *>(cc)[k];
+                    for (int k = 0; k < DIM; ++k) {
+                        cal[k] = cc[AOFF + k];
+                        cpos[k] = reinterpret_cast<const float *>(cc)[k];
+                    }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const double ph = (double)pair_f32<DIM, BASIS>(q32[p], cpos);
 #pragma unroll
                         for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
                     }
-                } else {
-                    double cpos[DIM];
+                }
+            } else {
+#pragma unroll 2
+                for (int c = 0; c < kept; ++c) {
+                    const double *cc = tile + c * ST;
+                    double cal[DIM], cpos[DIM];
 #pragma unroll
-                    for (int k = 0; k < DIM; ++k) cpos[k] = cc[k];
+                    for (int k = 0; k < DIM; ++k) {
+                        cal[k] = cc[AOFF + k];
+                        cpos[k] = cc[k];
+                    }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
                         const double ph = pair_f64<DIM, BASIS>(q64[p], cpos);
@@ -303,7 +325,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
 #pragma unroll
             for (int k = 0; k < DIM; ++k) acc[p][k] = __builtin_fma(wg[p], la[p][k], acc[p][k]);
     }
-    if (a.pairs && tid == 0 && n_eval) atomicAdd(a.pairs, n_eval * (unsigned long long)n_valid);
+    if (a.pairs && lane == 0 && n_eval) atomicAdd(a.pairs, n_eval);
 
 #pragma unroll
     for (int p = 0; p < P; ++p) {
@@ -317,7 +339,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                 a.out[o] = a.base ? a.base[o] - a.sign * acc[p][k] : (-a.sign) * acc[p][k];
             }
         } else {
-            const int64_t w = wbase + p * BLOCK + tid;
+            const int64_t w = wbase + (int64_t)wave * (64 * P) + p * 64 + lane;
 #pragma unroll
             for (int k = 0; k < DIM; ++k)
                 a.partial[((int64_t)split * DIM + k) * a.ld_part + w] = acc[p][k];
@@ -473,7 +495,6 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     a.sign = pb.sign;
     a.out = pb.out;
     a.ld_out = pb.ld_out ? pb.ld_out : pb.n_p;
-    a.dmax = dmax;
     a.n_work = pb.n_p;
 
     DevBuf work, nwork, partial, counts;
@@ -501,7 +522,9 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     }
 
     // Launch shape: P points per lane; split the control lists when there are too few blocks.
-    const bool mixed = pb.precision == RBF_MIXED;
+    // The FP32 pair form is compiled in when some level asks for it.
+    bool mixed = false;
+    for (int l = 0; l < pb.n_levels; ++l) mixed |= pb.lv[l].fp32 != 0;
     // Two points per lane share every control read from LDS; one point per lane gives twice the
     // workgroups, which balances better when there are few blocks (the cost of a block varies
     // with the number of controls near it).

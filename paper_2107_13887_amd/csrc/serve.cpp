@@ -3,12 +3,13 @@
 // Geometry. rbf_geom_create copies the surface and volume into the context's pool, computes the
 // wall distance when none is given (distance to the nearest surface point), and stores the volume
 // in blocks of VBLOCK points: the points are put in Z order (a space-filling curve over the
-// bounding box, so each block is spatially compact), cut into blocks, and the blocks are stored
-// by increasing smallest wall distance. The reduced volume of any request, {d < max D_l} (section
-// 4), is then inside a prefix of whole blocks whose end the host knows from the sorted block
-// minima, with no per-request compaction; and every kernel-sum workgroup takes one compact block,
-// which lets it skip the controls whose support misses the block. Results go back through the
-// permutation.
+// bounding box, so each block is spatially compact), cut into blocks, the blocks are stored by
+// increasing smallest wall distance, and the points inside each block by wall distance. The
+// reduced volume of any request, {d < max D_l} (section 4), is then inside a prefix of whole
+// blocks whose end the host knows from the sorted block minima, with no per-request compaction;
+// every kernel-sum workgroup takes one compact block, which lets it skip the controls whose
+// support misses the block, and each wave skips the levels none of its points reaches. Results
+// go back through the permutation.
 //
 // Requests. rbf_submit copies the request and queues it. Worker slots, each with its own HIP
 // stream, pull requests in arrival order as soon as they are free: a request is admitted when its
@@ -244,6 +245,59 @@ __global__ __launch_bounds__(256) void geo_gather(const int32_t *border, const i
     }
 }
 
+// Inside every stored block, order the points by wall distance (ties by slot, so by Z order):
+// a wave then holds points of similar distance, and one whose points all lie at or beyond a
+// level's support distance skips that level. One workgroup per block, bitonic sort in LDS.
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_blocksort(int32_t *perm, double *d_sorted, double *x_sorted,
+                                                     int64_t n_pad)
+{
+    static_assert(VBLOCK == 512, "two keys per lane");
+    __shared__ double key[VBLOCK];
+    __shared__ int32_t slot[VBLOCK];
+    const int64_t b0 = (int64_t)blockIdx.x * VBLOCK;
+    const int t = threadIdx.x;
+    for (int j = t; j < VBLOCK; j += 256) {
+        key[j] = d_sorted[b0 + j];
+        slot[j] = j;
+    }
+    __syncthreads();
+    for (int k = 2; k <= VBLOCK; k <<= 1)
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            const int i = (t / j) * 2 * j + (t % j), q = i + j;
+            const bool up = (i & k) == 0;
+            const bool gt = key[i] > key[q] || (key[i] == key[q] && slot[i] > slot[q]);
+            if (gt == up) {
+                const double kv = key[i];
+                key[i] = key[q];
+                key[q] = kv;
+                const int32_t sv = slot[i];
+                slot[i] = slot[q];
+                slot[q] = sv;
+            }
+            __syncthreads();
+        }
+    int32_t pv[2];
+    double dv[2], xvv[2][DIM];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int64_t src = b0 + slot[t + 256 * r];
+        pv[r] = perm[src];
+        dv[r] = d_sorted[src];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xvv[r][k] = x_sorted[k * n_pad + src];
+    }
+    __syncthreads();   // every read of the block is done before any slot is overwritten
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int64_t dst = b0 + t + 256 * r;
+        perm[dst] = pv[r];
+        d_sorted[dst] = dv[r];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) x_sorted[k * n_pad + dst] = xvv[r][k];
+    }
+}
+
 template <int DIM>
 rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const double *xv,
                           const double *dwall, hipStream_t s)
@@ -327,6 +381,8 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     hipLaunchKernelGGL(geo_gather<DIM>, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, s,
                        border.as<const int32_t>(), iin->as<const int32_t>(), d, xv, n_v, n_pad,
                        g.perm.as<int32_t>(), g.d_sorted.as<double>(), g.xv_sorted.as<double>());
+    hipLaunchKernelGGL(geo_blocksort<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<int32_t>(),
+                       g.d_sorted.as<double>(), g.xv_sorted.as<double>(), n_pad);
     RBF_HIP(hipGetLastError());
     RBF_HIP(hipStreamSynchronize(s));
     return RBF_OK;
@@ -345,7 +401,8 @@ uint64_t greedy_footprint(int dim, int64_t n_s, int64_t cap)
     const uint64_t cols = (uint64_t)std::min<int64_t>(n_s, cap);
     return sizeof(double) * (2 * (cols * (uint64_t)n_s + cols * (cols + 1) / 2) + (uint64_t)(3 * dim + 1) * n_s +
                              (uint64_t)(dim + 1) * cols + 2 * (uint64_t)cap) +
-           (uint64_t)n_s * 17 + sizeof(int64_t) * (uint64_t)cap + sizeof(double) * (uint64_t)cap * 2 * dim;
+           (uint64_t)n_s * 17 + sizeof(int64_t) * (uint64_t)cap + sizeof(double) * (uint64_t)cap * 2 * dim +
+           sizeof(double) * ((uint64_t)dim * n_s + (uint64_t)n_s / 256 + 1);   // FP32 error check
 }
 
 }  // namespace
@@ -576,7 +633,9 @@ rbf_status Server::run(Req &q, hipStream_t s)
     for (int l = 0; l < p.n_levels; ++l) {
         const double Dl = q.r.d_factor > 0.0 ? q.r.d_factor * cs->level_in_max[l] : q.r.D[l];
         if (cs->level_off[l + 1] == cs->level_off[l] || !(Dl > 0.0)) continue;
-        pb.lv[pb.n_levels++] = SumLevel{1.0 / p.radius[l], Dl, cs->level_off[l], cs->level_off[l + 1]};
+        // FP32 pairs only where the level's measured FP32 error at the surface allows it.
+        const bool f32 = p.precision == RBF_MIXED && cs->level_fp32_err[l] <= RBF_MIXED_TOL * cs->level_in_max[0];
+        pb.lv[pb.n_levels++] = SumLevel{1.0 / p.radius[l], Dl, cs->level_off[l], cs->level_off[l + 1], f32};
         dmax = std::max(dmax, Dl);
     }
     pb.ld_ctrl = cs->capacity;
@@ -687,7 +746,8 @@ rbf_status rbf_geom_create(rbf_ctx ctx, int32_t dim, int64_t n_s, const double *
 rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, const double *radius,
                                   const double *D, const int32_t *level_off, int64_t ld_ctrl,
                                   const double *xc, const double *alpha, double *dv,
-                                  int32_t precision, int32_t basis, void *stream)
+                                  int32_t precision, const int32_t *level_precision, int32_t basis,
+                                  void *stream)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
     Geometry *g = nullptr;
@@ -708,7 +768,7 @@ rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, 
         dmax = std::max(dmax, D[l]);
     }
     if (level_off[n_levels] > ld_ctrl) return fail(RBF_E_INVALID, "level_off exceeds ld_ctrl");
-    if (precision != RBF_FP64 && precision != RBF_MIXED) return fail(RBF_E_INVALID, "bad precision");
+    RBF_TRY(check_precision(precision, level_precision, n_levels));
     if (!basis_valid(basis)) return fail(RBF_E_INVALID, "unknown basis %d", basis);
     if (g->n_v == 0) return RBF_OK;
     if (!dv || (level_off[n_levels] > level_off[0] && (!xc || !alpha))) return fail(RBF_E_INVALID, "NULL device array");
@@ -716,7 +776,9 @@ rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, 
     SumProblem pb;
     pb.dim = g->dim;
     pb.n_levels = n_levels;
-    for (int l = 0; l < n_levels; ++l) pb.lv[l] = SumLevel{1.0 / radius[l], D[l], level_off[l], level_off[l + 1]};
+    for (int l = 0; l < n_levels; ++l)
+        pb.lv[l] = SumLevel{1.0 / radius[l], D[l], level_off[l], level_off[l + 1],
+                            (level_precision ? level_precision[l] : precision) == RBF_MIXED};
     pb.ld_ctrl = ld_ctrl;
     pb.xc = xc;
     pb.alpha = alpha;

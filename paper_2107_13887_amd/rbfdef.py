@@ -25,6 +25,16 @@ RBF_WENDLAND_C2, RBF_WENDLAND_C0, RBF_WENDLAND_C4, RBF_WENDLAND_C6 = 0, 1, 2, 3
 BASES = {"c2": RBF_WENDLAND_C2, "c0": RBF_WENDLAND_C0, "c4": RBF_WENDLAND_C4, "c6": RBF_WENDLAND_C6}
 
 
+def _precision(precision, n_levels: int):
+    """(precision code, per-level array or None) from "fp64", "mixed" or one of them per level."""
+    code = lambda p: RBF_MIXED if p == "mixed" else RBF_FP64
+    if isinstance(precision, str):
+        return code(precision), None
+    if len(precision) != n_levels:
+        raise ValueError("one precision per level")
+    return RBF_FP64, (_i32 * n_levels)(*[code(p) for p in precision])
+
+
 def _basis(name: str) -> int:
     if name not in BASES:
         raise ValueError(f"unknown basis {name!r}; one of {sorted(BASES)}")
@@ -50,7 +60,8 @@ class rbf_ctrl_set(ctypes.Structure):
                 ("e_final", _vp), ("n_levels_used", _i32), ("stop_reason", _i32),
                 ("level_off", _i32 * (MAX_LEVELS + 1)), ("level_stop", _i32 * MAX_LEVELS),
                 ("level_max_err", _f64 * MAX_LEVELS), ("level_in_max", _f64 * MAX_LEVELS),
-                ("level_seconds", _f64 * MAX_LEVELS), ("n_iterations", _i64)]
+                ("level_seconds", _f64 * MAX_LEVELS), ("level_fp32_err", _f64 * MAX_LEVELS),
+                ("n_iterations", _i64)]
 
 
 class rbf_request(ctypes.Structure):
@@ -74,13 +85,15 @@ _SIGS = {
                                  ctypes.POINTER(rbf_ctrl_set), _vp]),
     "rbf_solve_weights": (_i32, [_vp, _i32, _f64, _i64, _vp, _vp, _vp, _i32, _vp]),
     "rbf_volume_update": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
-                                 ctypes.POINTER(_i32), _i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32, _i32, _vp]),
+                                 ctypes.POINTER(_i32), _i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32,
+                                 ctypes.POINTER(_i32), _i32, _vp]),
     "rbf_evaluate": (_i32, [_vp, _i32, _f64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _f64, _vp, _i32, _i32,
                             _vp]),
     "rbf_geom_create": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_vp)]),
     "rbf_geom_release": (_i32, [_vp, _vp]),
     "rbf_geom_volume_update": (_i32, [_vp, _vp, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
-                                      ctypes.POINTER(_i32), _i64, _vp, _vp, _vp, _i32, _i32, _vp]),
+                                      ctypes.POINTER(_i32), _i64, _vp, _vp, _vp, _i32, ctypes.POINTER(_i32),
+                                      _i32, _vp]),
     "rbf_submit": (_i32, [_vp, ctypes.POINTER(rbf_request), ctypes.POINTER(_u64)]),
     "rbf_poll": (_i32, [_vp, _u64, ctypes.POINTER(rbf_req_info)]),
     "rbf_wait": (_i32, [_vp, _u64, ctypes.POINTER(rbf_req_info)]),
@@ -185,8 +198,11 @@ def rbf_now() -> float:
     return lib().rbf_now()
 
 
-def rbf_ctx_set_timing(ctx: int, enabled: bool) -> None:
-    _check(lib().rbf_ctx_set_timing(ctx, 1 if enabled else 0), "rbf_ctx_set_timing")
+def rbf_ctx_set_timing(ctx: int, enabled: bool, count_pairs: bool = False) -> None:
+    """Event timing of the kernel-sum launches; count_pairs adds the evaluated-pair counter (one
+    atomic per workgroup: keep it off while timing)."""
+    flags = (1 if enabled else 0) | (2 if count_pairs else 0)
+    _check(lib().rbf_ctx_set_timing(ctx, flags), "rbf_ctx_set_timing")
 
 
 def rbf_ctx_kernel_pairs(ctx: int, kernel: str) -> int:
@@ -223,6 +239,12 @@ class CtrlSet:
     status: int
     level_in_max: List[float] = field(default_factory=list)    # max ||dS_l|| per level input
     level_seconds: List[float] = field(default_factory=list)
+    level_fp32_err: List[float] = field(default_factory=list)   # FP32 error at the surface (mixed)
+
+    def fp32_levels(self, tol: float = 1e-6) -> List[bool]:
+        """Levels whose measured FP32 error is at most tol max ||dS|| (the serving path's rule)."""
+        return [0.0 < e <= tol * self.level_in_max[0] if self.level_fp32_err else False
+                for e in self.level_fp32_err[: self.n_levels_used]]
 
     @property
     def total(self) -> int:
@@ -296,7 +318,8 @@ def rbf_greedy_select(ctx: int, xs, ds, radius: Sequence[float], eps: float, rho
                    level_max_err=[out.level_max_err[l] for l in range(len(radius))],
                    n_levels_used=nl, n_iterations=out.n_iterations, status=st,
                    level_in_max=[out.level_in_max[l] for l in range(len(radius))],
-                   level_seconds=[out.level_seconds[l] for l in range(len(radius))])
+                   level_seconds=[out.level_seconds[l] for l in range(len(radius))],
+                   level_fp32_err=[out.level_fp32_err[l] for l in range(len(radius))])
 
 
 def rbf_solve_weights(ctx: int, radius: float, xc, dsc, alpha=None, stream=None, basis: str = "c2"):
@@ -314,9 +337,10 @@ def rbf_solve_weights(ctx: int, radius: float, xc, dsc, alpha=None, stream=None,
 
 
 def rbf_volume_update(ctx: int, radius: Sequence[float], D: Sequence[float], level_off: Sequence[int],
-                      xc, alpha, xv, dwall, dv=None, precision: str = "fp64", stream=None,
+                      xc, alpha, xv, dwall, dv=None, precision="fp64", stream=None,
                       basis: str = "c2"):
-    """Enqueue the psi-weighted volume update; returns dv (written asynchronously on the stream)."""
+    """Enqueue the psi-weighted volume update; returns dv (written asynchronously on the stream).
+    precision: "fp64", "mixed", or a list with one of them per level."""
     import torch
 
     dim, n_v = xv.shape
@@ -338,8 +362,9 @@ def rbf_volume_update(ctx: int, radius: Sequence[float], D: Sequence[float], lev
     r = (_f64 * nl)(*[float(x) for x in radius])
     d = (_f64 * nl)(*[float(x) for x in D])
     off = (_i32 * (nl + 1))(*[int(x) for x in level_off])
+    prec, levels = _precision(precision, nl)
     _check(lib().rbf_volume_update(ctx, dim, nl, r, d, off, ldc, pxc, pa, n_v, pxv, pd, pdv,
-                                   RBF_MIXED if precision == "mixed" else RBF_FP64, _basis(basis), _stream(stream)),
+                                   prec, levels, _basis(basis), _stream(stream)),
            "rbf_volume_update")
     return dv
 
@@ -379,10 +404,10 @@ def rbf_geom_create(ctx: int, xs, xv, dwall=None) -> int:
 
 
 def rbf_geom_volume_update(ctx: int, geom: int, radius: Sequence[float], D: Sequence[float],
-                           level_off: Sequence[int], xc, alpha, dv, precision: str = "fp64", stream=None,
+                           level_off: Sequence[int], xc, alpha, dv, precision="fp64", stream=None,
                            basis: str = "c2"):
-    """Enqueue the volume update on a resident geometry (prefix of its wall-distance order);
-    dv is [dim, n_v] in the geometry's original point order."""
+    """Enqueue the volume update on a resident geometry; dv is [dim, n_v] in the geometry's
+    original point order. precision: "fp64", "mixed", or a list with one of them per level."""
     nl = len(radius)
     if len(level_off) != nl + 1:
         raise ValueError("level_off must have n_levels + 1 entries")
@@ -398,8 +423,9 @@ def rbf_geom_volume_update(ctx: int, geom: int, radius: Sequence[float], D: Sequ
     r = (_f64 * nl)(*[float(x) for x in radius])
     d = (_f64 * nl)(*[float(x) for x in D])
     off = (_i32 * (nl + 1))(*[int(x) for x in level_off])
-    _check(lib().rbf_geom_volume_update(ctx, geom, nl, r, d, off, ldc, pxc, pa, pdv,
-                                        RBF_MIXED if precision == "mixed" else RBF_FP64, _basis(basis), _stream(stream)),
+    prec, levels = _precision(precision, nl)
+    _check(lib().rbf_geom_volume_update(ctx, geom, nl, r, d, off, ldc, pxc, pa, pdv, prec, levels,
+                                        _basis(basis), _stream(stream)),
            "rbf_geom_volume_update")
     return dv
 
@@ -469,6 +495,7 @@ def _fill_ctrl(r: Request):
     r.out.n_iterations = oc.n_iterations
     r.out.level_in_max = [oc.level_in_max[l] for l in range(nl)]
     r.out.level_seconds = [oc.level_seconds[l] for l in range(nl)]
+    r.out.level_fp32_err = [oc.level_fp32_err[l] for l in range(nl)]
 
 
 def rbf_poll(ctx: int, r: Request) -> rbf_req_info:

@@ -50,7 +50,7 @@ def test_culled_resident_volume(gctx, orc, dim, n_s, n_v, radius, D):
     ref = orc.volume(w.radius, D, res.level_off, xc, res.alpha, w.xv, w.dwall)
     geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
     dv = torch.full((dim, n_v), float("nan"), dtype=torch.float64, device="cuda:0")
-    rbfdef.rbf_ctx_set_timing(gctx, True)
+    rbfdef.rbf_ctx_set_timing(gctx, True, count_pairs=True)
     rbfdef.rbf_geom_volume_update(gctx, geom, w.radius, D, list(res.level_off), to_dev(xc),
                                   to_dev(res.alpha), dv)
     torch.cuda.synchronize()
@@ -84,7 +84,7 @@ def test_culling_takes_effect(gctx, orc):
     D = [3.0]
     geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
     dv = torch.empty((2, w.n_v), dtype=torch.float64, device="cuda:0")
-    rbfdef.rbf_ctx_set_timing(gctx, True)
+    rbfdef.rbf_ctx_set_timing(gctx, True, count_pairs=True)
     rbfdef.rbf_geom_volume_update(gctx, geom, w.radius, D, list(res.level_off), to_dev(xc),
                                   to_dev(res.alpha), dv)
     torch.cuda.synchronize()
