@@ -15,11 +15,12 @@
 // back substitution L^T alpha = y, and the level residual dS_{l+1} = dS_l - Phi_sC alpha is then
 // recomputed from alpha by the FP64 kernel sum (the same quantity the paper's loop produces).
 //
-// Execution. A level runs as one persistent cooperative kernel: a select phase (one workgroup:
-// argmax of the per-tile maxima, stop tests, row extraction, pivot) and an update phase (all
-// workgroups, 64 surface points per tile: new column, error update, tile argmax), separated by
-// grid-wide barriers, so an iteration costs two barriers instead of two kernel launches. When a
-// cooperative launch is not possible the same phases run as two kernels per iteration.
+// Execution. An iteration is a select phase (one workgroup: argmax of the per-tile maxima, stop
+// tests, row extraction, pivot) and an update phase (all workgroups, 64 surface points per tile:
+// new column, error update, tile argmax). On small surfaces a level runs as one persistent
+// cooperative kernel whose last workgroup to arrive at a barrier runs the select phase, so an
+// iteration costs one barrier; on large surfaces (or when a cooperative launch is impossible) the
+// two phases run as two kernel launches per iteration.
 // Reductions run in a fixed order; squared norms are formed without fused multiply-adds so they
 // equal the textbook formula term by term.
 #include <hip/hip_cooperative_groups.h>
@@ -41,6 +42,7 @@ constexpr int UPB = 64;       // surface points per tile (one per lane)
 constexpr int UWAVES = 4;     // waves per workgroup, each a slice of the dot product
 constexpr int NT = UPB * UWAVES;
 constexpr int LCHUNK = 2048;  // Newton row entries staged per LDS pass
+constexpr int64_t LEAN_MAX_TILES = 256;   // largest surface (in tiles) run by the persistent kernel
 
 struct GState {
     int64_t n;        // finished columns (control points) of the level
@@ -769,7 +771,11 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     const int64_t g = (n_s + UPB - 1) / UPB;
 
     DevBuf bV, bL, bE, bR, bR2, bSel, bPart, bState, bCoef, bHist, bFlag, bSeeds;
-    RBF_TRY(bV.get(pool, sizeof(double) * (size_t)cols * (size_t)((n_s + UPB - 1) / UPB) * UPB));
+    // Columns per tile in the basis, odd so that the tiles' regions start at odd multiples of
+    // 512 bytes: workgroups that read the same column of their tiles at the same moment then fall
+    // on different memory channels instead of one.
+    const int64_t ldt = cols | 1;
+    RBF_TRY(bV.get(pool, sizeof(double) * (size_t)ldt * (size_t)((n_s + UPB - 1) / UPB) * UPB));
     RBF_TRY(bL.get(pool, sizeof(double) * (size_t)(cols * (cols + 1) / 2 + 1)));
     RBF_TRY(bE.get(pool, sizeof(double) * DIM * (size_t)n_s));
     RBF_TRY(bR.get(pool, sizeof(double) * DIM * (size_t)n_s));
@@ -810,11 +816,18 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     RBF_HIP(hipMemsetAsync(st, 0, sizeof(GState), s));
     RBF_HIP(hipMemcpyAsync(R, ds, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
 
-    // Execution mode: "lean" (one barrier per iteration, default), "cg" (cooperative-groups grid
-    // barriers) or "kernels" (two launches per iteration).
+    // Execution mode: "lean" (one barrier per iteration), "cg" (cooperative-groups grid
+    // barriers) or "kernels" (two launches per iteration). Default: the persistent kernel while the surface has at most LEAN_MAX_TILES tiles (one
+    // workgroup per CU; latency-bound iterations, where launches would dominate), two launches per
+    // iteration beyond that: there the basis stream is the cost, and fresh launches stream it at
+    // about twice the rate of the persistent kernel, whose per-workgroup release and acquire each
+    // iteration write back and invalidate the L2 of every XCD.
     const char *mode_env = getenv("RBF_GREEDY_MODE");
-    const int mode = getenv("RBF_NO_COOP") ? 2 : (mode_env && !strcmp(mode_env, "cg")) ? 1
-                   : (mode_env && !strcmp(mode_env, "kernels")) ? 2 : 0;
+    const int mode = getenv("RBF_NO_COOP") ? 2
+                   : (mode_env && !strcmp(mode_env, "cg")) ? 1
+                   : (mode_env && !strcmp(mode_env, "kernels")) ? 2
+                   : (mode_env && !strcmp(mode_env, "lean")) ? 0
+                   : (g > LEAN_MAX_TILES ? 2 : 0);
     const int coop_max = mode == 2 ? 0
                        : cooperative_blocks(mode == 0 ? (const void *)g_level_lean<DIM> : (const void *)g_level<DIM>,
                                             ctx->n_cu);
@@ -826,7 +839,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     a.n_s = n_s;
     a.basis = prm.basis;
     a.V = bV.as<double>();
-    a.ldt = cols;
+    a.ldt = ldt;
     a.Lpack = bL.as<double>();
     a.coef = bCoef.as<double>();
     a.ld_coef = cols;
@@ -870,7 +883,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
                               n0 <= a.cap_level &&
                               std::equal(lc.ctrl.begin(), lc.ctrl.end(), seeds_h.begin() + seed_off[l]);
             if (same) {
-                RBF_HIP(hipMemcpy2DAsync(a.V, sizeof(double) * cols * UPB, lc.V.ptr, sizeof(double) * n0 * UPB,
+                RBF_HIP(hipMemcpy2DAsync(a.V, sizeof(double) * ldt * UPB, lc.V.ptr, sizeof(double) * n0 * UPB,
                                          sizeof(double) * n0 * UPB, g, hipMemcpyDeviceToDevice, s));
                 RBF_HIP(hipMemcpyAsync(a.Lpack, lc.L.ptr, sizeof(double) * (n0 * (n0 + 1) / 2),
                                        hipMemcpyDeviceToDevice, s));
@@ -1005,7 +1018,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
             lc.n = 0;
             if (n > 0 && lc.V.get(pool, sizeof(double) * n * g * UPB) == RBF_OK &&
                 lc.L.get(pool, sizeof(double) * (n * (n + 1) / 2)) == RBF_OK) {
-                RBF_HIP(hipMemcpy2DAsync(lc.V.ptr, sizeof(double) * n * UPB, a.V, sizeof(double) * cols * UPB,
+                RBF_HIP(hipMemcpy2DAsync(lc.V.ptr, sizeof(double) * n * UPB, a.V, sizeof(double) * ldt * UPB,
                                          sizeof(double) * n * UPB, g, hipMemcpyDeviceToDevice, s));
                 RBF_HIP(hipMemcpyAsync(lc.L.ptr, a.Lpack, sizeof(double) * (n * (n + 1) / 2),
                                        hipMemcpyDeviceToDevice, s));
