@@ -154,18 +154,32 @@ Pool::~Pool()
 }
 
 // ---- kernel timers ----------------------------------------------------------------------------
+hipEvent_t KernelTimers::take()
+{
+    std::lock_guard<std::mutex> lk(mu);
+    if (!spare.empty()) {
+        hipEvent_t e = spare.back();
+        spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
 void KernelTimers::begin(hipEvent_t *a, hipStream_t s)
 {
     *a = nullptr;
     if (!enabled) return;
-    if (hipEventCreate(a) != hipSuccess || hipEventRecord(*a, s) != hipSuccess) *a = nullptr;
+    *a = take();
+    if (*a && hipEventRecord(*a, s) != hipSuccess) *a = nullptr;
 }
 
 void KernelTimers::end(const char *name, hipEvent_t a, hipStream_t s)
 {
     if (!enabled || !a) return;
-    hipEvent_t b;
-    if (hipEventCreate(&b) != hipSuccess) return;
+    hipEvent_t b = take();
+    if (!b) return;
     (void)hipEventRecord(b, s);
     std::lock_guard<std::mutex> lk(mu);
     pending.push_back(Pending{name, a, b});
@@ -185,6 +199,12 @@ unsigned long long *KernelTimers::counter(const char *name)
 
 KernelTimers::~KernelTimers()
 {
+    for (auto &p : pending) {
+        (void)hipEventSynchronize(p.b);
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (hipEvent_t e : spare) (void)hipEventDestroy(e);
     if (dev_count) (void)hipFree(dev_count);
 }
 
@@ -199,8 +219,8 @@ void KernelTimers::resolve()
             t.first += ms;
             t.second += 1;
         }
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
+        spare.push_back(p.a);
+        spare.push_back(p.b);
     }
     pending.clear();
 }

@@ -905,7 +905,9 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         }
         bool done = false;
         if (coop_max > 0) {
-            const unsigned G = (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, coop_max));
+            int64_t gmax = coop_max;
+            if (const char *e = getenv("RBF_GREEDY_WGS")) gmax = std::max<int64_t>(1, std::min<int64_t>(gmax, atoi(e)));
+            const unsigned G = (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, gmax));
             // Persistent kernels of concurrent requests must fit on the device together, or their
             // spinning workgroups could wait for each other's unscheduled ones.
             CoopTicket gate(ctx, G, coop_max);

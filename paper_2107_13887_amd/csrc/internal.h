@@ -110,6 +110,7 @@ struct Geometry {
     // Volume stored in blocks of VBLOCK Z-ordered points, blocks by increasing smallest wall
     // distance; n_pad = whole blocks, padding slots have perm -1 and d = +inf.
     DevBuf xs, xv_sorted, d_sorted, perm;   // perm: stored slot -> caller's index
+    DevBuf block_box;                       // [n_pad / VBLOCK][2 dim]: min, max of each block's points
     int64_t n_pad = 0;
     std::vector<double> block_dmin;         // host: smallest wall distance of each stored block
     // Control sets of the last finished request (warm start), host copies per level.
@@ -132,6 +133,8 @@ struct KernelTimers {
     bool count_pairs = false;
     struct Pending { std::string name; hipEvent_t a, b; };
     std::vector<Pending> pending;
+    std::vector<hipEvent_t> spare;   // resolved events, reused (no event creation per launch)
+    hipEvent_t take();
     std::map<std::string, std::pair<double, int64_t>> total;   // name -> (ms, launches)
     // Evaluated-pair counters of the kernel sums, one device slot per timed kernel name.
     static constexpr int N_COUNT = 16;
@@ -198,6 +201,7 @@ struct SumProblem {
     // +0.0 through perm. n_active < 0: not used.
     const int32_t *perm = nullptr;
     int64_t n_active = -1;
+    const double *block_box = nullptr;   // [n_pad / VBLOCK][2 dim] box of each stored block
 };
 
 // Enqueues the whole evaluation on `s`; scratch comes from the pool and is released

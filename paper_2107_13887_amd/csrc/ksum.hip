@@ -55,6 +55,8 @@ struct KArgs {
     double *partial;                // [n_split][DIM][ld_part]
     int64_t ld_part;
     unsigned long long *pairs;      // evaluated (point, control) pairs are added here, or null
+    int64_t n_live;                 // rows from here on need no level (-1: every row may)
+    const double *block_box;        // resident geometry: box of every stored block [nb][2 DIM], or null
 };
 
 // A control is dropped for a workgroup when its squared distance to the workgroup's box, in units
@@ -85,6 +87,11 @@ __device__ __forceinline__ double psi_w(double d, double D)
 
 __device__ __forceinline__ void split_range(const SumLevel &L, int s, int S, int64_t &cb, int64_t &ce)
 {
+    if (S == 1) {
+        cb = L.c_begin;
+        ce = L.c_end;
+        return;
+    }
     int64_t nc = L.c_end - L.c_begin;
     cb = L.c_begin + (nc * s) / S;
     ce = L.c_begin + (nc * (s + 1)) / S;
@@ -129,58 +136,89 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
     constexpr int ST = 2 * DIM;                         // doubles per control in LDS
     constexpr int AOFF = DIM;                           // offset of the weights
     constexpr int NW = BLOCK / 64;                      // waves per workgroup
+    constexpr int ML = RBF_MAX_LEVELS;
     __shared__ double tile[TILE * ST];
     __shared__ double origin[DIM];
     __shared__ double wbox[NW][2 * DIM];
-    __shared__ double box[2 * DIM];                     // the level's box: min[DIM], max[DIM]
+    __shared__ double box[ML][2 * DIM];                 // per level: min[DIM], max[DIM]
     __shared__ int wcnt[NW];
+    __shared__ int64_t vs[ML + 1], cb[ML];              // the workgroup's control stream (below)
+    __shared__ double sbox[ML][2 * DIM];                // level boxes scaled by 1 / R_l
+    __shared__ double s_inv_r[ML];
+    __shared__ int wlc[NW][ML];                         // kept controls per wave and level
+    __shared__ int seg[ML + 1];                         // level segments of the kept tile
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n_work = a.n_work_dev ? *a.n_work_dev : a.n_work;
     const int64_t wbase = (int64_t)blockIdx.x * (BLOCK * P);
     if (wbase >= n_work) return;
     const int split = blockIdx.y;
+    // Rows from n_live on lie beyond every level's support (resident volume past its reduced
+    // prefix): the workgroup only writes zeros.
+    const bool live = a.n_live < 0 || wbase < a.n_live;
 
-    int64_t idx[P];
+    // Point rows: wave v takes the 64 P consecutive rows from wbase + 64 P v, lane-contiguous for
+    // each p, so a wave holds neighbouring points of the stored order. Every load of the point
+    // data is issued here, once.
+    int64_t idx[P], oi[P];
     bool ok[P];
-    double dw[P], acc[P][DIM];
-    // Point rows: wave v takes the 64 P consecutive rows from wbase + 64 P v, lane-contiguous
-    // for each p, so a wave holds neighbouring points of the stored order.
+    double dw[P], acc[P][DIM], xq[P][DIM];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int64_t w = wbase + (int64_t)wave * (64 * P) + p * 64 + lane;
         ok[p] = w < n_work;
         idx[p] = ok[p] ? (a.work ? (int64_t)a.work[w] : w) : 0;
-        dw[p] = (a.dwall && ok[p]) ? a.dwall[idx[p]] : 0.0;
+        oi[p] = (ok[p] && a.out_perm) ? (int64_t)a.out_perm[idx[p]] : idx[p];
+        dw[p] = (live && a.dwall && ok[p]) ? a.dwall[idx[p]] : 0.0;
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) acc[p][k] = 0.0;
+        for (int k = 0; k < DIM; ++k) {
+            xq[p][k] = (live && ok[p]) ? a.xp[k * a.ld_p + idx[p]] : 0.0;
+            acc[p][k] = 0.0;
+        }
     }
-    if (MIXED && tid == 0) {
-        const int64_t i0 = a.work ? (int64_t)a.work[wbase] : wbase;
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) origin[k] = a.xp[k * a.ld_p + i0];
-    }
-    int wave_pts = 0;                                   // valid points of this wave
-#pragma unroll
-    for (int p = 0; p < P; ++p) wave_pts += __popcll(__ballot(ok[p]));
     unsigned long long n_eval = 0;                      // pairs this wave evaluated
 
-    double box_d = -1.0;                                // support distance the box was built for
-    bool wave_need = false;
-    for (int l = 0; l < a.n_levels; ++l) {
-        // The coordinates are read again for every level (cache hits) rather than held in
-        // registers across levels.
-        double wg[P], xq[P][DIM];
+    if (live) {
+        if (MIXED && tid == 0) {
+            const int64_t i0 = a.work ? (int64_t)a.work[wbase] : wbase;
 #pragma unroll
-        for (int p = 0; p < P; ++p) {
-            wg[p] = a.dwall ? psi_w(dw[p], a.lv[l].D) : 1.0;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) xq[p][k] = a.xp[k * a.ld_p + idx[p]];
+            for (int k = 0; k < DIM; ++k) origin[k] = a.xp[k * a.ld_p + i0];
         }
-        // Box of the points this level weights (psi > 0), rebuilt when the support distance
-        // changes (every level shares it when D is fixed).
-        const double dl = a.dwall ? a.lv[l].D : 0.0;
-        if (l == 0 || dl != box_d) {
-            box_d = dl;
+        int wave_pts = 0;                               // valid points of this wave
+#pragma unroll
+        for (int p = 0; p < P; ++p) wave_pts += __popcll(__ballot(ok[p]));
+
+        // Per level: the box of the points it weights (psi > 0) and, per wave, whether any of its
+        // points needs it. Levels sharing the support distance share the box.
+        unsigned int wave_need = 0;
+        if (a.block_box) {
+            // Resident geometry: the stored block's box (all its points) bounds every level's
+            // points, with no reduction; a level is used when some point of the wave needs it.
+            const double *bb = a.block_box + (wbase / VBLOCK) * 2 * DIM;
+            for (int l = 0; l < a.n_levels; ++l) {
+                bool need = false;
+#pragma unroll
+                for (int p = 0; p < P; ++p) need |= ok[p] && psi_w(dw[p], a.lv[l].D) > 0.0;
+                if (__ballot(need) != 0ull) wave_need |= 1u << l;
+                if (tid < 2 * DIM) box[l][tid] = bb[tid];
+            }
+            if (lane == 0) wcnt[wave] = (int)wave_need;
+            __syncthreads();
+            unsigned int any = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) any |= (unsigned int)wcnt[w];
+            // Levels no wave needs get an empty box (the control stream leaves them out).
+            if (tid < a.n_levels * 2 * DIM) {
+                const int l = tid / (2 * DIM), k = tid % (2 * DIM);
+                if (!((any >> l) & 1u)) box[l][k] = k < DIM ? HUGE_VAL : -HUGE_VAL;
+            }
+        }
+        for (int l = 0; l < (a.block_box ? 0 : a.n_levels); ++l) {
+            const double dl = a.dwall ? a.lv[l].D : 0.0;
+            if (l > 0 && dl == (a.dwall ? a.lv[l - 1].D : 0.0)) {
+                wave_need |= ((wave_need >> (l - 1)) & 1u) << l;
+                if (tid < 2 * DIM) box[l][tid] = box[l - 1][tid];
+                continue;
+            }
             double lo[DIM], hi[DIM];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
@@ -190,7 +228,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
             bool need = false;
 #pragma unroll
             for (int p = 0; p < P; ++p)
-                if (ok[p] && wg[p] > 0.0) {
+                if (ok[p] && (!a.dwall || psi_w(dw[p], dl) > 0.0)) {
                     need = true;
 #pragma unroll
                     for (int k = 0; k < DIM; ++k) {
@@ -198,7 +236,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                         hi[k] = fmax(hi[k], xq[p][k]);
                     }
                 }
-            wave_need = __ballot(need) != 0ull;          // the same in every lane of the wave
+            if (__ballot(need) != 0ull) wave_need |= 1u << l;
 #pragma unroll
             for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
@@ -206,7 +244,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                     lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
                     hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
                 }
-            __syncthreads();                            // earlier readers of box are done
+            __syncthreads();                            // earlier readers of wbox are done
             if (lane == 0)
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
@@ -218,50 +256,71 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                 double v = wbox[0][tid];
 #pragma unroll
                 for (int w = 1; w < NW; ++w) v = tid < DIM ? fmin(v, wbox[w][tid]) : fmax(v, wbox[w][tid]);
-                box[tid] = v;
+                box[l][tid] = v;
             }
-            __syncthreads();
         }
-        if (!(box[0] <= box[DIM])) continue;            // no point of the workgroup needs the level
-        const bool f32 = MIXED && a.lv[l].fp32;
-        const double inv_r = a.lv[l].inv_r;
-        int64_t cb, ce;
-        split_range(a.lv[l], split, a.n_split, cb, ce);
-        double la[P][DIM];
-        double q64[P][DIM];
-        float q32[P][DIM];
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                q32[p][k] = (float)((xq[p][k] - (MIXED ? origin[k] : 0.0)) * inv_r);
-                q64[p][k] = xq[p][k] * inv_r;
-                la[p][k] = 0.0;
+        __syncthreads();
+
+        // This split's controls of every level the workgroup needs, as one stream in level
+        // order: [vs[l], vs[l + 1]) holds level l's range starting at control cb[l].
+        if (tid == 0) {
+            vs[0] = 0;
+            for (int l = 0; l < a.n_levels; ++l) {
+                int64_t c0, c1;
+                split_range(a.lv[l], split, a.n_split, c0, c1);
+                cb[l] = c0;
+                vs[l + 1] = vs[l] + (box[l][0] <= box[l][DIM] ? c1 - c0 : 0);
             }
-        for (int64_t t0 = cb; t0 < ce; t0 += TILE) {
-            const int nt = (int)min<int64_t>(TILE, ce - t0);
+        }
+        if (tid < a.n_levels) s_inv_r[tid] = a.lv[tid].inv_r;
+        if (tid < a.n_levels * 2 * DIM) {
+            const int l = tid / (2 * DIM), k = tid % (2 * DIM);
+            sbox[l][k] = box[l][k] * a.lv[l].inv_r;
+        }
+        __syncthreads();
+        const int64_t total = vs[a.n_levels];
+
+        for (int64_t v0 = 0; v0 < total; v0 += TILE) {
+            const int nt = (int)min<int64_t>(TILE, total - v0);
             __syncthreads();
-            // Stage the tile: keep the controls whose support reaches the box, in order.
+            // Stage the tile: keep the controls whose support reaches their level's box, in order.
             double xck[DIM], ack[DIM];
             bool keep = false;
+            int lv_me = 0;
             if (tid < nt) {
+                const int64_t v = v0 + tid;
+                while (lv_me + 1 < a.n_levels && vs[lv_me + 1] <= v) ++lv_me;
+                const int64_t c = cb[lv_me] + (v - vs[lv_me]);
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
-                    xck[k] = a.xc[k * a.ld_ctrl + t0 + tid];
-                    ack[k] = a.alpha[k * a.ld_ctrl + t0 + tid];
+                    xck[k] = a.xc[k * a.ld_ctrl + c];
+                    ack[k] = a.alpha[k * a.ld_ctrl + c];
                 }
+                const double inv_r = s_inv_r[lv_me];
                 double g2 = 0.0;
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
-                    const double c = xck[k] * inv_r;
-                    const double gap = fmax(fmax(box[k] * inv_r - c, c - box[DIM + k] * inv_r), 0.0);
+                    const double cs = xck[k] * inv_r;
+                    const double gap = fmax(fmax(sbox[lv_me][k] - cs, cs - sbox[lv_me][DIM + k]), 0.0);
                     g2 = __builtin_fma(gap, gap, g2);
                 }
                 keep = g2 < CULL2;
             }
             const unsigned long long m = __ballot(keep);
             if (lane == 0) wcnt[wave] = __popcll(m);
+            for (int l = 0; l < a.n_levels; ++l) {
+                const unsigned long long ml = __ballot(keep && lv_me == l);
+                if (lane == 0) wlc[wave][l] = __popcll(ml);
+            }
             __syncthreads();
+            if (tid == 0) {
+                int run = 0;
+                seg[0] = 0;
+                for (int l = 0; l < a.n_levels; ++l) {
+                    for (int w = 0; w < NW; ++w) run += wlc[w][l];
+                    seg[l + 1] = run;
+                }
+            }
             int pos = __popcll(m & ((1ull << lane) - 1ull));
             int kept = 0;
 #pragma unroll
@@ -272,6 +331,8 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
             kept = __builtin_amdgcn_readfirstlane(kept);   // the same in every lane: a scalar loop bound
             if (keep) {
                 double *dst = tile + pos * ST;
+                const double inv_r = s_inv_r[lv_me];
+                const bool f32 = MIXED && a.lv[lv_me].fp32;
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
                     if (f32) reinterpret_cast<float *>(dst)[k] = (float)((xck[k] - origin[k]) * inv_r);
@@ -281,49 +342,73 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                 for (int k = 0; k < DIM; ++k) dst[AOFF + k] = ack[k];
             }
             __syncthreads();
-            if (!wave_need) continue;                   // no point of this wave needs the level
-            n_eval += (unsigned long long)kept * (unsigned long long)wave_pts;
-            if (f32) {
-#pragma unroll 2
-                for (int c = 0; c < kept; ++c) {
-                    const double *cc = tile + c * ST;
-                    double cal[DIM];
-                    float cpos[DIM];
+            // The kept controls of one level are consecutive: one pair loop per level segment.
+            for (int l = 0; l < a.n_levels; ++l) {
+                const int c0 = __builtin_amdgcn_readfirstlane(seg[l]);
+                const int c1 = __builtin_amdgcn_readfirstlane(seg[l + 1]);
+                if (c1 > c0 && ((wave_need >> l) & 1u)) {
+                    n_eval += (unsigned long long)(c1 - c0) * (unsigned long long)wave_pts;
+                    const double inv_r = a.lv[l].inv_r;
+                    double la[P][DIM];
 #pragma unroll
-                    for (int k = 0; k < DIM; ++k) {
-                        cal[k] = cc[AOFF + k];
-                        cpos[k] = reinterpret_cast<const float *>(cc)[k];
+                    for (int p = 0; p < P; ++p)
+#pragma unroll
+                        for (int k = 0; k < DIM; ++k) la[p][k] = 0.0;
+                    if (MIXED && a.lv[l].fp32) {
+                        float q32[P][DIM];
+#pragma unroll
+                        for (int p = 0; p < P; ++p)
+#pragma unroll
+                            for (int k = 0; k < DIM; ++k) q32[p][k] = (float)((xq[p][k] - origin[k]) * inv_r);
+#pragma unroll 2
+                        for (int c = c0; c < c1; ++c) {
+                            const double *cc = tile + c * ST;
+                            double cal[DIM];
+                            float cpos[DIM];
+#pragma unroll
+                            for (int k = 0; k < DIM; ++k) {
+                                cal[k] = cc[AOFF + k];
+                                cpos[k] = reinterpret_cast<const float *>(cc)[k];
+                            }
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const double ph = (double)pair_f32<DIM, BASIS>(q32[p], cpos);
+#pragma unroll
+                                for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
+                            }
+                        }
+                    } else {
+                        double q64[P][DIM];
+#pragma unroll
+                        for (int p = 0; p < P; ++p)
+#pragma unroll
+                            for (int k = 0; k < DIM; ++k) q64[p][k] = xq[p][k] * inv_r;
+#pragma unroll 2
+                        for (int c = c0; c < c1; ++c) {
+                            const double *cc = tile + c * ST;
+                            double cal[DIM], cpos[DIM];
+#pragma unroll
+                            for (int k = 0; k < DIM; ++k) {
+                                cal[k] = cc[AOFF + k];
+                                cpos[k] = cc[k];
+                            }
+#pragma unroll
+                            for (int p = 0; p < P; ++p) {
+                                const double ph = pair_f64<DIM, BASIS>(q64[p], cpos);
+#pragma unroll
+                                for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
+                            }
+                        }
                     }
 #pragma unroll
                     for (int p = 0; p < P; ++p) {
-                        const double ph = (double)pair_f32<DIM, BASIS>(q32[p], cpos);
+                        const double wgl = a.dwall ? psi_w(dw[p], a.lv[l].D) : 1.0;
 #pragma unroll
-                        for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
-                    }
-                }
-            } else {
-#pragma unroll 2
-                for (int c = 0; c < kept; ++c) {
-                    const double *cc = tile + c * ST;
-                    double cal[DIM], cpos[DIM];
-#pragma unroll
-                    for (int k = 0; k < DIM; ++k) {
-                        cal[k] = cc[AOFF + k];
-                        cpos[k] = cc[k];
-                    }
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const double ph = pair_f64<DIM, BASIS>(q64[p], cpos);
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
+                        for (int k = 0; k < DIM; ++k) acc[p][k] = __builtin_fma(wgl, la[p][k], acc[p][k]);
                     }
                 }
             }
         }
-#pragma unroll
-        for (int p = 0; p < P; ++p)
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) acc[p][k] = __builtin_fma(wg[p], la[p][k], acc[p][k]);
     }
     if (a.pairs && lane == 0 && n_eval) atomicAdd(a.pairs, n_eval);
 
@@ -331,11 +416,10 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
     for (int p = 0; p < P; ++p) {
         if (!ok[p]) continue;
         if (a.n_split == 1) {
-            const int64_t oi = a.out_perm ? (int64_t)a.out_perm[idx[p]] : idx[p];
-            if (oi < 0) continue;
+            if (oi[p] < 0) continue;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                const int64_t o = k * a.ld_out + oi;
+                const int64_t o = k * a.ld_out + oi[p];
                 a.out[o] = a.base ? a.base[o] - a.sign * acc[p][k] : (-a.sign) * acc[p][k];
             }
         } else {
@@ -477,6 +561,7 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     const int DIM = pb.dim;
     if (pb.n_p == 0) return RBF_OK;
     KArgs a{};
+    a.n_live = -1;
     a.n_levels = pb.n_levels;
     int64_t nc_max = 0;
     double dmax = 0.0;
@@ -500,10 +585,12 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     DevBuf work, nwork, partial, counts;
     int64_t n_rows = pb.n_p;    // rows the kernel-sum grid covers
     if (pb.dwall && pb.n_active >= 0) {
-        // Resident geometry in wall-distance order: results go out through perm. The grid covers
-        // every point; blocks past the reduced prefix find no point with psi > 0, skip every
-        // level and write +0.0, so no separate zero-fill is launched.
+        // Resident geometry: results go out through perm. The grid covers every point; the
+        // workgroups past the reduced prefix only write +0.0, so no separate zero-fill is
+        // launched.
         a.out_perm = pb.perm;
+        a.n_live = pb.n_active;
+        a.block_box = pb.block_box;
     } else if (pb.dwall) {
         RBF_TRY(nwork.get(ctx->pool.get(), sizeof(int64_t)));
         {

@@ -298,6 +298,44 @@ __global__ __launch_bounds__(256) void geo_blocksort(int32_t *perm, double *d_so
     }
 }
 
+// Box (min, max per coordinate) of the points of every stored block, padding excluded.
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_blockbox(const int32_t *perm, const double *x_sorted, int64_t n_pad,
+                                                    double *box)
+{
+    __shared__ double red[256][2 * DIM];
+    const int64_t b0 = (int64_t)blockIdx.x * VBLOCK;
+    double lo[DIM], hi[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        lo[k] = HUGE_VAL;
+        hi[k] = -HUGE_VAL;
+    }
+    for (int j = threadIdx.x; j < VBLOCK; j += 256)
+        if (perm[b0 + j] >= 0)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                lo[k] = fmin(lo[k], x_sorted[k * n_pad + b0 + j]);
+                hi[k] = fmax(hi[k], x_sorted[k * n_pad + b0 + j]);
+            }
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        red[threadIdx.x][k] = lo[k];
+        red[threadIdx.x][DIM + k] = hi[k];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                red[threadIdx.x][k] = fmin(red[threadIdx.x][k], red[threadIdx.x + w][k]);
+                red[threadIdx.x][DIM + k] = fmax(red[threadIdx.x][DIM + k], red[threadIdx.x + w][DIM + k]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 2 * DIM) box[blockIdx.x * 2 * DIM + threadIdx.x] = red[0][threadIdx.x];
+}
+
 template <int DIM>
 rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const double *xv,
                           const double *dwall, hipStream_t s)
@@ -313,7 +351,7 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     RBF_TRY(g.xv_sorted.get(pool, sizeof(double) * DIM * std::max<int64_t>(1, n_pad)));
     RBF_TRY(g.d_sorted.get(pool, sizeof(double) * std::max<int64_t>(1, n_pad)));
     RBF_TRY(g.perm.get(pool, sizeof(int32_t) * std::max<int64_t>(1, n_pad)));
-    g.bytes = sizeof(double) * (DIM * (n_s + n_pad) + n_pad) + sizeof(int32_t) * n_pad;
+    g.bytes = sizeof(double) * (DIM * (n_s + n_pad) + n_pad + 2 * DIM * nb) + sizeof(int32_t) * n_pad;
     if (n_v == 0) return RBF_OK;
     DevBuf dtmp, part, k0, k1, i0, i1, hist, bmin, border;
     const double *d = dwall;
@@ -383,6 +421,9 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
                        g.perm.as<int32_t>(), g.d_sorted.as<double>(), g.xv_sorted.as<double>());
     hipLaunchKernelGGL(geo_blocksort<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<int32_t>(),
                        g.d_sorted.as<double>(), g.xv_sorted.as<double>(), n_pad);
+    RBF_TRY(g.block_box.get(pool, sizeof(double) * 2 * DIM * nb));
+    hipLaunchKernelGGL(geo_blockbox<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<const int32_t>(),
+                       g.xv_sorted.as<const double>(), n_pad, g.block_box.as<double>());
     RBF_HIP(hipGetLastError());
     RBF_HIP(hipStreamSynchronize(s));
     return RBF_OK;
@@ -648,6 +689,7 @@ rbf_status Server::run(Req &q, hipStream_t s)
     pb.dwall = g.d_sorted.as<double>();
     pb.perm = g.perm.as<int32_t>();
     pb.n_active = prefix_for(g, dmax);
+    pb.block_box = g.block_box.as<double>();
     pb.out = q.r.dv;
     pb.sign = -1.0;
     pb.precision = p.precision;
@@ -789,6 +831,7 @@ rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, 
     pb.dwall = g->d_sorted.as<double>();
     pb.perm = g->perm.as<int32_t>();
     pb.n_active = prefix_for(*g, dmax);
+    pb.block_box = g->block_box.as<double>();
     pb.out = dv;
     pb.sign = -1.0;
     pb.precision = precision;
