@@ -188,9 +188,10 @@ rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, in
  * Serving: resident geometries and asynchronous deformation requests with continuous batching.
  * A geometry (surface + volume + wall distance) is copied once into the pool and kept, the
  * volume stored in spatially compact blocks of 512 points (Z order) sorted by their smallest wall
- * distance, so each request's reduced volume lies in a prefix of whole blocks and each block can
- * skip the controls whose support misses it. The device copy takes 8 (dim + 1) + 4 bytes per
- * volume point (rounded up to whole blocks) plus 8 dim per surface point. Requests that arrive
+ * distance, each block sorted by wall distance too, so each request's reduced volume lies in a
+ * prefix of whole blocks; the bounding box of every 64 stored points is kept so that they can
+ * skip the controls whose support misses them. The device copy takes 8 (dim + 1) + 4 + dim / 4
+ * bytes per volume point (rounded up to whole blocks) plus 8 dim per surface point. Requests that arrive
  * while others run are admitted as soon as a slot and enough of the HBM budget are free; their
  * kernels overlap on separate streams. A request with warm_start seeds each level with the
  * control set the geometry's previous request selected (successive icing steps).

@@ -110,7 +110,7 @@ struct Geometry {
     // Volume stored in blocks of VBLOCK Z-ordered points, blocks by increasing smallest wall
     // distance; n_pad = whole blocks, padding slots have perm -1 and d = +inf.
     DevBuf xs, xv_sorted, d_sorted, perm;   // perm: stored slot -> caller's index
-    DevBuf block_box;                       // [n_pad / VBLOCK][2 dim]: min, max of each block's points
+    DevBuf block_box;                       // [n_pad / BOXROWS][2 dim]: min, max of every BOXROWS stored points
     int64_t n_pad = 0;
     std::vector<double> block_dmin;         // host: smallest wall distance of each stored block
     // Control sets of the last finished request (warm start), host copies per level.
@@ -170,6 +170,8 @@ namespace rbf {
 // ---- kernel sums (ksum.hip) ---------------------------------------------------------------------
 // Points per stored volume block: one kernel-sum workgroup (256 lanes x 2 points).
 constexpr int VBLOCK = 512;
+// Stored points per kept bounding box (one wave of the resident kernel sum).
+constexpr int BOXROWS = 64;
 
 struct SumLevel {
     double inv_r;     // 1 / R_l
@@ -201,7 +203,7 @@ struct SumProblem {
     // +0.0 through perm. n_active < 0: not used.
     const int32_t *perm = nullptr;
     int64_t n_active = -1;
-    const double *block_box = nullptr;   // [n_pad / VBLOCK][2 dim] box of each stored block
+    const double *block_box = nullptr;   // [n_pad / BOXROWS][2 dim] box of every BOXROWS stored points
 };
 
 // Enqueues the whole evaluation on `s`; scratch comes from the pool and is released

@@ -56,7 +56,7 @@ struct KArgs {
     int64_t ld_part;
     unsigned long long *pairs;      // evaluated (point, control) pairs are added here, or null
     int64_t n_live;                 // rows from here on need no level (-1: every row may)
-    const double *block_box;        // resident geometry: box of every stored block [nb][2 DIM], or null
+    const double *block_box;        // resident geometry: box of every BOXROWS stored rows [n / BOXROWS][2 DIM], or null
 };
 
 // A control is dropped for a workgroup when its squared distance to the workgroup's box, in units
@@ -128,6 +128,106 @@ __device__ __forceinline__ float pair_f32(const float (&q)[DIM], const float *c)
     return wendland_t<BASIS, float>(eta, t);
 }
 
+// Adds phi * alpha over the staged controls [c0, c1) of level l (consecutive in the tile) to the
+// level's running sum la, for the P points of this lane. A level's sum runs over its controls in
+// stream order whatever the tiling, and culled controls only drop exact zeros, so every kernel
+// here gives the same bits.
+template <int DIM, int P, bool MIXED, int BASIS>
+__device__ __forceinline__ void level_accum(const KArgs &a, int l, const double *tile, int c0, int c1,
+                                            const double (&xq)[P][DIM], const double (&org)[DIM],
+                                            double (&la)[P][DIM])
+{
+    constexpr int ST = 2 * DIM;
+    constexpr int AOFF = DIM;
+    const double inv_r = a.lv[l].inv_r;
+    if (MIXED && a.lv[l].fp32) {
+        float q32[P][DIM];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) q32[p][k] = (float)((xq[p][k] - org[k]) * inv_r);
+#pragma unroll 2
+        for (int c = c0; c < c1; ++c) {
+            const double *cc = tile + c * ST;
+            double cal[DIM];
+            float cpos[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                cal[k] = cc[AOFF + k];
+                cpos[k] = reinterpret_cast<const float *>(cc)[k];
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double ph = (double)pair_f32<DIM, BASIS>(q32[p], cpos);
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
+            }
+        }
+    } else {
+        double q64[P][DIM];
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) q64[p][k] = xq[p][k] * inv_r;
+#pragma unroll 2
+        for (int c = c0; c < c1; ++c) {
+            const double *cc = tile + c * ST;
+            double cal[DIM], cpos[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                cal[k] = cc[AOFF + k];
+                cpos[k] = cc[k];
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const double ph = pair_f64<DIM, BASIS>(q64[p], cpos);
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
+            }
+        }
+    }
+}
+
+// acc += psi(d / D_l) la for the finished level l (psi = 1 without wall distances); la = 0.
+template <int DIM, int P>
+__device__ __forceinline__ void level_flush(const KArgs &a, int l, const double (&dw)[P], double (&la)[P][DIM],
+                                            double (&acc)[P][DIM])
+{
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const double wgl = a.dwall ? psi_w(dw[p], a.lv[l].D) : 1.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            acc[p][k] = __builtin_fma(wgl, la[p][k], acc[p][k]);
+            la[p][k] = 0.0;
+        }
+    }
+}
+
+// Final values (one split) or split partials of the P points of this lane.
+template <int DIM, int P>
+__device__ __forceinline__ void store_rows(const KArgs &a, int64_t rbase, int lane, const bool (&ok)[P],
+                                           const int64_t (&oi)[P], const double (&acc)[P][DIM])
+{
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        if (!ok[p]) continue;
+        if (a.n_split == 1) {
+            if (oi[p] < 0) continue;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const int64_t o = k * a.ld_out + oi[p];
+                a.out[o] = a.base ? a.base[o] - a.sign * acc[p][k] : (-a.sign) * acc[p][k];
+            }
+        } else {
+            const int64_t w = rbase + p * 64 + lane;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k)
+                a.partial[((int64_t)blockIdx.y * DIM + k) * a.ld_part + w] = acc[p][k];
+        }
+    }
+}
+
 template <int DIM, int P, bool MIXED, int BASIS>
 __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
 {
@@ -191,15 +291,28 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
         // points needs it. Levels sharing the support distance share the box.
         unsigned int wave_need = 0;
         if (a.block_box) {
-            // Resident geometry: the stored block's box (all its points) bounds every level's
-            // points, with no reduction; a level is used when some point of the wave needs it.
-            const double *bb = a.block_box + (wbase / VBLOCK) * 2 * DIM;
+            // Resident geometry: the stored boxes of the workgroup's rows (all their points) bound
+            // every level's points, with no reduction; a level is used when some point of the wave
+            // needs it.
+            constexpr int NB = BLOCK * P / BOXROWS;     // stored boxes per workgroup
+            const double *bb = a.block_box + (wbase / BOXROWS) * 2 * DIM;
+            double bv = 0.0;
+            if (tid < 2 * DIM) {
+                const int k = tid % DIM;
+                const bool lo = tid < DIM;
+                bv = bb[tid];
+#pragma unroll
+                for (int j = 1; j < NB; ++j) {
+                    const double v = bb[j * 2 * DIM + (lo ? k : DIM + k)];
+                    bv = lo ? fmin(bv, v) : fmax(bv, v);
+                }
+            }
             for (int l = 0; l < a.n_levels; ++l) {
                 bool need = false;
 #pragma unroll
                 for (int p = 0; p < P; ++p) need |= ok[p] && psi_w(dw[p], a.lv[l].D) > 0.0;
                 if (__ballot(need) != 0ull) wave_need |= 1u << l;
-                if (tid < 2 * DIM) box[l][tid] = bb[tid];
+                if (tid < 2 * DIM) box[l][tid] = bv;
             }
             if (lane == 0) wcnt[wave] = (int)wave_need;
             __syncthreads();
@@ -279,6 +392,14 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
         }
         __syncthreads();
         const int64_t total = vs[a.n_levels];
+        double org[DIM], la[P][DIM];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) org[k] = MIXED ? origin[k] : 0.0;
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) la[p][k] = 0.0;
+        int open_l = -1;                                // level whose sum la holds
 
         for (int64_t v0 = 0; v0 < total; v0 += TILE) {
             const int nt = (int)min<int64_t>(TILE, total - v0);
@@ -348,87 +469,18 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
                 const int c1 = __builtin_amdgcn_readfirstlane(seg[l + 1]);
                 if (c1 > c0 && ((wave_need >> l) & 1u)) {
                     n_eval += (unsigned long long)(c1 - c0) * (unsigned long long)wave_pts;
-                    const double inv_r = a.lv[l].inv_r;
-                    double la[P][DIM];
-#pragma unroll
-                    for (int p = 0; p < P; ++p)
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) la[p][k] = 0.0;
-                    if (MIXED && a.lv[l].fp32) {
-                        float q32[P][DIM];
-#pragma unroll
-                        for (int p = 0; p < P; ++p)
-#pragma unroll
-                            for (int k = 0; k < DIM; ++k) q32[p][k] = (float)((xq[p][k] - origin[k]) * inv_r);
-#pragma unroll 2
-                        for (int c = c0; c < c1; ++c) {
-                            const double *cc = tile + c * ST;
-                            double cal[DIM];
-                            float cpos[DIM];
-#pragma unroll
-                            for (int k = 0; k < DIM; ++k) {
-                                cal[k] = cc[AOFF + k];
-                                cpos[k] = reinterpret_cast<const float *>(cc)[k];
-                            }
-#pragma unroll
-                            for (int p = 0; p < P; ++p) {
-                                const double ph = (double)pair_f32<DIM, BASIS>(q32[p], cpos);
-#pragma unroll
-                                for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
-                            }
-                        }
-                    } else {
-                        double q64[P][DIM];
-#pragma unroll
-                        for (int p = 0; p < P; ++p)
-#pragma unroll
-                            for (int k = 0; k < DIM; ++k) q64[p][k] = xq[p][k] * inv_r;
-#pragma unroll 2
-                        for (int c = c0; c < c1; ++c) {
-                            const double *cc = tile + c * ST;
-                            double cal[DIM], cpos[DIM];
-#pragma unroll
-                            for (int k = 0; k < DIM; ++k) {
-                                cal[k] = cc[AOFF + k];
-                                cpos[k] = cc[k];
-                            }
-#pragma unroll
-                            for (int p = 0; p < P; ++p) {
-                                const double ph = pair_f64<DIM, BASIS>(q64[p], cpos);
-#pragma unroll
-                                for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
-                            }
-                        }
+                    if (l != open_l) {
+                        if (open_l >= 0) level_flush<DIM, P>(a, open_l, dw, la, acc);
+                        open_l = l;
                     }
-#pragma unroll
-                    for (int p = 0; p < P; ++p) {
-                        const double wgl = a.dwall ? psi_w(dw[p], a.lv[l].D) : 1.0;
-#pragma unroll
-                        for (int k = 0; k < DIM; ++k) acc[p][k] = __builtin_fma(wgl, la[p][k], acc[p][k]);
-                    }
+                    level_accum<DIM, P, MIXED, BASIS>(a, l, tile, c0, c1, xq, org, la);
                 }
             }
         }
+        if (open_l >= 0) level_flush<DIM, P>(a, open_l, dw, la, acc);
     }
     if (a.pairs && lane == 0 && n_eval) atomicAdd(a.pairs, n_eval);
-
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-        if (!ok[p]) continue;
-        if (a.n_split == 1) {
-            if (oi[p] < 0) continue;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                const int64_t o = k * a.ld_out + oi[p];
-                a.out[o] = a.base ? a.base[o] - a.sign * acc[p][k] : (-a.sign) * acc[p][k];
-            }
-        } else {
-            const int64_t w = wbase + (int64_t)wave * (64 * P) + p * 64 + lane;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k)
-                a.partial[((int64_t)split * DIM + k) * a.ld_part + w] = acc[p][k];
-        }
-    }
+    store_rows<DIM, P>(a, wbase + (int64_t)wave * (64 * P), lane, ok, oi, acc);
 }
 
 // Sum the split partials in split order and write the final values.

@@ -298,42 +298,36 @@ __global__ __launch_bounds__(256) void geo_blocksort(int32_t *perm, double *d_so
     }
 }
 
-// Box (min, max per coordinate) of the points of every stored block, padding excluded.
+// Box (min, max per coordinate) of every BOXROWS consecutive stored points, padding excluded
+// (all padding: an empty box, min +inf and max -inf). One wave per box.
 template <int DIM>
 __global__ __launch_bounds__(256) void geo_blockbox(const int32_t *perm, const double *x_sorted, int64_t n_pad,
                                                     double *box)
 {
-    __shared__ double red[256][2 * DIM];
-    const int64_t b0 = (int64_t)blockIdx.x * VBLOCK;
+    static_assert(BOXROWS == 64, "one row per lane");
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;   // n_pad is a multiple of 256
+    const bool pt = perm[j] >= 0;
     double lo[DIM], hi[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        lo[k] = HUGE_VAL;
-        hi[k] = -HUGE_VAL;
+        const double x = x_sorted[k * n_pad + j];
+        lo[k] = pt ? x : HUGE_VAL;
+        hi[k] = pt ? x : -HUGE_VAL;
     }
-    for (int j = threadIdx.x; j < VBLOCK; j += 256)
-        if (perm[b0 + j] >= 0)
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                lo[k] = fmin(lo[k], x_sorted[k * n_pad + b0 + j]);
-                hi[k] = fmax(hi[k], x_sorted[k * n_pad + b0 + j]);
-            }
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off));
+        }
+    const int lane = threadIdx.x & 63;
+    double *b = box + (j / BOXROWS) * 2 * DIM;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {
-        red[threadIdx.x][k] = lo[k];
-        red[threadIdx.x][DIM + k] = hi[k];
+        if (lane == k) b[k] = lo[k];
+        if (lane == DIM + k) b[DIM + k] = hi[k];
     }
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                red[threadIdx.x][k] = fmin(red[threadIdx.x][k], red[threadIdx.x + w][k]);
-                red[threadIdx.x][DIM + k] = fmax(red[threadIdx.x][DIM + k], red[threadIdx.x + w][DIM + k]);
-            }
-        __syncthreads();
-    }
-    if (threadIdx.x < 2 * DIM) box[blockIdx.x * 2 * DIM + threadIdx.x] = red[0][threadIdx.x];
 }
 
 template <int DIM>
@@ -351,7 +345,7 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     RBF_TRY(g.xv_sorted.get(pool, sizeof(double) * DIM * std::max<int64_t>(1, n_pad)));
     RBF_TRY(g.d_sorted.get(pool, sizeof(double) * std::max<int64_t>(1, n_pad)));
     RBF_TRY(g.perm.get(pool, sizeof(int32_t) * std::max<int64_t>(1, n_pad)));
-    g.bytes = sizeof(double) * (DIM * (n_s + n_pad) + n_pad + 2 * DIM * nb) + sizeof(int32_t) * n_pad;
+    g.bytes = sizeof(double) * (DIM * (n_s + n_pad) + n_pad + 2 * DIM * (n_pad / BOXROWS)) + sizeof(int32_t) * n_pad;
     if (n_v == 0) return RBF_OK;
     DevBuf dtmp, part, k0, k1, i0, i1, hist, bmin, border;
     const double *d = dwall;
@@ -421,8 +415,8 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
                        g.perm.as<int32_t>(), g.d_sorted.as<double>(), g.xv_sorted.as<double>());
     hipLaunchKernelGGL(geo_blocksort<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<int32_t>(),
                        g.d_sorted.as<double>(), g.xv_sorted.as<double>(), n_pad);
-    RBF_TRY(g.block_box.get(pool, sizeof(double) * 2 * DIM * nb));
-    hipLaunchKernelGGL(geo_blockbox<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<const int32_t>(),
+    RBF_TRY(g.block_box.get(pool, sizeof(double) * 2 * DIM * (n_pad / BOXROWS)));
+    hipLaunchKernelGGL(geo_blockbox<DIM>, dim3((unsigned)(n_pad / 256)), dim3(256), 0, s, g.perm.as<const int32_t>(),
                        g.xv_sorted.as<const double>(), n_pad, g.block_box.as<double>());
     RBF_HIP(hipGetLastError());
     RBF_HIP(hipStreamSynchronize(s));
