@@ -87,9 +87,10 @@ struct GArgs {
 
 struct SelShared {
     Cand sh[UWAVES];
-    double red[NT];
+    double red[UWAVES];
     int32_t stop, skip;
-    int64_t n;
+    int64_t n, p;
+    double m2;
 };
 
 struct UpdShared {
@@ -219,52 +220,90 @@ __global__ __launch_bounds__(NT) void g_begin(GState *st, const Cand *part, int6
 // Select phase (one workgroup): finish the pending column, choose the next point (argmax or a
 // forced seed), apply the stop tests, extract the Newton row l = V[p, 0:n] as row n of the
 // Cholesky factor and form the pivot d = sqrt(phi(0) - l.l) and the coefficients y_n = E_p / d.
+// Two rounds of memory reads: the level state with the per-tile maxima, then the row with E_p.
 template <int DIM>
 __device__ void select_phase(const GArgs &a, int64_t forced, SelShared &s)
 {
     GState *st = a.st;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int32_t stop0 = 0, go0 = 0;
+    int64_t n0 = 0;
+    double target2 = 0.0;
     if (threadIdx.x == 0) {
-        s.skip = st->stop >= 0;            // level already finished
-        if (!s.skip && st->go) {           // the previous update completed column n
-            st->n += 1;
+        stop0 = st->stop;
+        go0 = st->go;
+        n0 = st->n;
+        target2 = st->target2;
+    }
+    if (forced < 0) {
+        double bm = -1.0;
+        int64_t bi = -1;
+        for (int64_t b = threadIdx.x; b < a.g; b += NT) {
+            const Cand c = a.part[b];
+            if (better(c.m2, c.idx, bm, bi)) {
+                bm = c.m2;
+                bi = c.idx;
+            }
+        }
+        wave_argmax(bm, bi);
+        if (lane == 0) s.sh[w] = Cand{bm, bi};
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s.skip = stop0 >= 0;               // level already finished
+        if (!s.skip && go0) {              // the previous update completed column n
+            n0 += 1;
+            st->n = n0;
             st->go = 0;
         }
-        s.n = st->n;
-    }
-    __syncthreads();
-    if (s.skip) return;
-    const int64_t n = s.n;
-    double m2 = 0.0;
-    int64_t p = forced;
-    if (forced < 0) block_argmax(a.part, a.g, m2, p, s.sh);
-    if (threadIdx.x == 0) {
-        int32_t stop = -1;
+        s.n = n0;
+        double m2 = 0.0;
+        int64_t p = forced;
         if (forced < 0) {
-            if (p < 0) stop = RBF_STOP_ALL_SELECTED;
-            else if (m2 < st->target2) stop = RBF_STOP_EPS;
+            m2 = s.sh[0].m2;
+            p = s.sh[0].idx;
+            for (int k = 1; k < UWAVES; ++k)
+                if (better(s.sh[k].m2, s.sh[k].idx, m2, p)) {
+                    m2 = s.sh[k].m2;
+                    p = s.sh[k].idx;
+                }
         }
-        if (stop < 0 && n >= a.cap_level) stop = RBF_STOP_CAP;
+        int32_t stop = -1;
+        if (!s.skip) {
+            if (forced < 0) {
+                if (p < 0) stop = RBF_STOP_ALL_SELECTED;
+                else if (m2 < target2) stop = RBF_STOP_EPS;
+            }
+            if (stop < 0 && n0 >= a.cap_level) stop = RBF_STOP_CAP;
+            if (stop >= 0) st->stop = stop;
+        }
         s.stop = stop;
-        if (stop >= 0) st->stop = stop;
+        s.p = p;
+        s.m2 = m2;
     }
     __syncthreads();
-    if (s.stop >= 0) return;
+    if (s.skip || s.stop >= 0) return;
+    const int64_t n = s.n, p = s.p;
 
     double *row = a.Lpack + (n * (n + 1)) / 2;
+    double ep[DIM];
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ep[k] = a.E[k * a.n_s + p];
     double part_ll = 0.0;
     for (int64_t j = threadIdx.x; j < n; j += NT) {
         const double v = a.V[((p / UPB) * a.ldt + j) * UPB + (p % UPB)];
         row[j] = v;
         part_ll = __builtin_fma(v, v, part_ll);
     }
-    s.red[threadIdx.x] = part_ll;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part_ll += __shfl_xor(part_ll, off, 64);
+    if (lane == 0) s.red[w] = part_ll;
     __syncthreads();
-    for (int k = NT / 2; k > 0; k >>= 1) {
-        if (threadIdx.x < k) s.red[threadIdx.x] += s.red[threadIdx.x + k];
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
-        const double d2 = 1.0 - s.red[0];     // phi(0) - l.l
+        double ll = s.red[0];
+        for (int k = 1; k < UWAVES; ++k) ll += s.red[k];
+        const double d2 = 1.0 - ll;       // phi(0) - l.l
         // l.l carries about (n + 1) ulps of rounding: a pivot below that is zero (breakdown).
         if (!(d2 > (double)(n + 1) * 0x1p-52)) {
             st->stop = RBF_STOP_BREAKDOWN;
@@ -275,14 +314,14 @@ __device__ void select_phase(const GArgs &a, int64_t forced, SelShared &s)
             st->d = d;
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                const double c = a.E[k * a.n_s + p] / d;
+                const double c = ep[k] / d;
                 st->c[k] = c;
                 a.coef[k * a.ld_coef + n] = c;
             }
             a.ctrl[n] = p;
             a.sel[p] = 1;
             if (forced < 0) {
-                if (st->n_iter < a.hist_cap) a.hist[st->n_iter] = sqrt(m2);
+                if (st->n_iter < a.hist_cap) a.hist[st->n_iter] = sqrt(s.m2);
                 st->n_iter += 1;
             }
             st->go = 1;

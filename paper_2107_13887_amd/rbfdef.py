@@ -146,6 +146,9 @@ def _stream(stream) -> int:
     import torch
 
     if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)   # no Stream object per call
+        if raw is not None:
+            return raw(torch.cuda.current_device())
         return torch.cuda.current_stream().cuda_stream
     if isinstance(stream, int):
         return stream

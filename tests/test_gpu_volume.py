@@ -143,3 +143,12 @@ def test_evaluate_matches_oracle(gctx, orc, dim):
     torch.cuda.synchronize()
     assert normwise(out.cpu().numpy(), ref) <= 1e-12
     assert np.abs(res.cpu().numpy() - (base - ref)).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_binding_uses_the_current_stream():
+    """The binding enqueues on torch's current stream, default or not."""
+    assert rbfdef._stream(None) == torch.cuda.current_stream().cuda_stream
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        assert rbfdef._stream(None) == s.cuda_stream == torch.cuda.current_stream().cuda_stream
+    assert rbfdef._stream(s) == s.cuda_stream
