@@ -32,6 +32,7 @@ METRIC = ("RBF evals/s (volume update: reduced-volume points x control points pe
           "outside the compact support are skipped, not computed), greedy time-to-eps, p50/p99 "
           "request latency")
 VALU_LANE_OPS = 256 * 64 * 2.4e9          # 256 CUs x 64 lanes x 2.4 GHz
+HBM_PEAK_GBS = 8000.0                     # MI355X HBM3E
 # Minimal VALU issue slots per (point, control) pair with the Wendland C2 basis: dim subtractions,
 # the squared distance (dim multiply-adds), the square root (a quarter-rate op: 4 slots), 1 - eta,
 # the clamp at 0, t^2 and t^4, 4 eta + 1, the product, and dim accumulating multiply-adds; points
@@ -425,6 +426,13 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, cs, radius, D, off, args.basis, big)
 
     used = cs.n_levels_used
+    # The greedy's Newton-basis stream (HBM-bound on large surfaces): an iteration with n finished
+    # columns reads the N_s x n basis and writes one column, and reads/writes E and reads x_s.
+    g_bytes = 0
+    for l in range(used):
+        m = n_c[l] if l < len(n_c) else 0
+        g_bytes += 8 * w.n_s * (m * (m - 1) // 2) + m * w.n_s * (9 + 24 * w.dim)
+    g_time = statistics.median(greedy_t)
     rec = {
         "metric": METRIC,
         "value": value,
@@ -447,6 +455,11 @@ def main():
         "greedy_time_to_eps_s": statistics.median(greedy_t),
         "greedy_iterations": cs.n_iterations,
         "greedy_iterations_per_s": cs.n_iterations / statistics.median(greedy_t),
+        "greedy_roofline": {"bound": "hbm", "achieved": g_bytes / g_time / 1e9, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": g_bytes / g_time / 1e9 / HBM_PEAK_GBS,
+                            "algorithmic_bytes": g_bytes,
+                            "work_unit": "Newton-basis stream of every iteration (N_s x n read, one "
+                                         "column written, E and x_s), whole greedy call timed"},
         "greedy_levels": [{"controls": n_c[l] if l < len(n_c) else 0, "seconds": cs.level_seconds[l],
                            "max_err_in": cs.level_in_max[l], "max_err_out": cs.level_max_err[l]}
                           for l in range(used)],
