@@ -426,6 +426,37 @@ def main():
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, cs, radius, D, off, args.basis, big)
 
     used = cs.n_levels_used
+    # Dense FP64 solve (blocked Cholesky, trailing updates on FP64 MFMA): n^3/3 flops of the
+    # factorization plus the dim triangular pairs, on the step's largest level and on the first
+    # min(N_s, 4000) surface points with the widest radius (a dense SPD matrix).
+    dense = []
+    big_l = max(range(used), key=lambda l: n_c[l]) if used else 0
+    sets = [("largest level of the step", cs.xc[:, off[big_l]:off[big_l + 1]].contiguous(),
+             ds[:, cs.ctrl_idx[off[big_l]:off[big_l + 1]]].contiguous(), radius[big_l])]
+    nd = min(w.n_s, 4000)
+    sets.append((f"first {nd} surface points", xs[:, :nd].contiguous(), ds[:, :nd].contiguous(), w.radius[0]))
+    for label, sx, sd, rr in sets:
+        nn = sx.shape[1]
+        if nn < 2:
+            continue
+        alpha_d = torch.empty_like(sx)
+        ms = _median_ms(stream, lambda: rbfdef.rbf_solve_weights(ctx, rr, sx, sd, alpha_d, basis=args.basis), 5)
+        flops = nn ** 3 / 3 + 2 * w.dim * nn * nn
+        dense.append({"points": nn, "set": label, "ms": ms, "tflops": flops / (ms / 1e3) / 1e12,
+                      "frac_of_fp64_mfma": flops / (ms / 1e3) / 78.6e12})
+    # The greedy's per-iteration floor: one 64-point tile, every point selected (eps 0), so each
+    # iteration is all synchronization and no streaming.
+    n_tiny = min(64, w.n_s)
+    tiny = lambda: rbfdef.rbf_greedy_select(ctx, xs[:, :n_tiny].contiguous(), ds[:, :n_tiny].contiguous(),
+                                            [w.radius[0]], 0.0, rho=w.rho, cap=n_tiny, seeds=[[0]],
+                                            precision="fp64", want_residual=False, basis=args.basis)
+    tiny()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ct = tiny()
+    torch.cuda.synchronize()
+    floor_us = (time.perf_counter() - t0) / max(ct.n_iterations, 1) * 1e6
+
     # The greedy's Newton-basis stream (HBM-bound on large surfaces): an iteration with n finished
     # columns reads the N_s x n basis and writes one column, and reads/writes E and reads x_s.
     g_bytes = 0
@@ -460,6 +491,8 @@ def main():
                             "algorithmic_bytes": g_bytes,
                             "work_unit": "Newton-basis stream of every iteration (N_s x n read, one "
                                          "column written, E and x_s), whole greedy call timed"},
+        "greedy_iteration_floor_us": floor_us,
+        "dense_solve": dense,
         "greedy_levels": [{"controls": n_c[l] if l < len(n_c) else 0, "seconds": cs.level_seconds[l],
                            "max_err_in": cs.level_in_max[l], "max_err_out": cs.level_max_err[l]}
                           for l in range(used)],

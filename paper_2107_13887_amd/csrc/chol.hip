@@ -1,8 +1,9 @@
 // Dense FP64 weight solve Phi_cc alpha = dS_c (eq. (9) on a given point set) on gfx950.
 //
 // Blocked right-looking Cholesky with 64x64 blocks on a row-major padded matrix:
-//   for each block column k:  L_kk = chol(A_kk)            (one workgroup, LDS)
-//                             L_ik = A_ik L_kk^-T           (panel, FP64 MFMA with inv(L_kk))
+//   for each block column k:  L_kk = chol(A_kk)            (one wave, a row per lane)
+//                             L_ik = A_ik L_kk^-T           (panel: one wave per row block,
+//                                                            a row per lane, L_kk in LDS)
 //                             A_ij -= L_ik L_jk^T, i >= j > k  (trailing update, FP64 MFMA)
 // then blocked forward and backward substitution for the dim right-hand sides. The trailing
 // update carries the n^3/3 flops and runs on v_mfma_f64_16x16x4_f64: each 256-lane workgroup
@@ -55,54 +56,53 @@ __global__ __launch_bounds__(256) void c_build(const double *xc, int64_t n, int6
     }
 }
 
-// Factor the diagonal block in LDS and store L_kk and inv(L_kk) (lower triangular).
-__global__ __launch_bounds__(256) void c_diag(double *A, int64_t lda, int64_t k0, double *Linv,
-                                              int32_t *bad)
+// Lane l's value of v, in every lane.
+__device__ __forceinline__ double lane_value(double v, int l)
 {
-    __shared__ double a[NB][NB + 1];
-    __shared__ double x[NB][NB + 1];
-    const int t = threadIdx.x;
-    for (int e = t; e < NB * NB; e += 256) {
-        int r = e / NB, c = e % NB;
-        a[r][c] = c <= r ? A[(k0 + r) * lda + k0 + c] : 0.0;
-    }
-    __syncthreads();
+    const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Factor the diagonal block: one wave, lane i holds row i in registers. At step j the pivot is
+// read from lane j, column j is scaled in every lane and written once to LDS, and each lane
+// subtracts L[i][j] L[c][j] from its entries c > j with L[c][j] read as an LDS broadcast.
+// Entries above the diagonal are left out of every read that matters and are not stored.
+__global__ __launch_bounds__(NB) void c_diag(double *A, int64_t lda, int64_t k0, int32_t *bad)
+{
+    __shared__ __align__(16) double col[NB];
+    const int i = threadIdx.x;
+    double *ar = A + (k0 + i) * lda + k0;
+    double r[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) r[c] = c <= i ? ar[c] : 0.0;
+    bool sing = false;
+#pragma unroll
     for (int j = 0; j < NB; ++j) {
-        if (t == 0) {
-            double d = a[j][j];
-            // A pivot within rounding of zero (below (index + 1) ulps of phi(0) = 1) is singular.
-            if (!(d > (double)(k0 + j + 1) * 0x1p-52)) {
-                *bad = 1;
-                d = 1.0;
-            }
-            a[j][j] = sqrt(d);
+        double d = lane_value(r[j], j);
+        // A pivot within rounding of zero (below (index + 1) ulps of phi(0) = 1) is singular.
+        if (!(d > (double)(k0 + j + 1) * 0x1p-52)) {
+            sing = true;
+            d = 1.0;
         }
-        __syncthreads();
-        const double djj = a[j][j];
-        for (int i = j + 1 + t; i < NB; i += 256) a[i][j] /= djj;
-        __syncthreads();
-        // rank-one update of the remaining lower triangle
-        for (int e = t; e < NB * NB; e += 256) {
-            int r = e / NB, c = e % NB;
-            if (c > j && r >= c) a[r][c] = __builtin_fma(-a[r][j], a[c][j], a[r][c]);
-        }
-        __syncthreads();
-    }
-    // inverse of the lower-triangular factor, one column per lane
-    if (t < NB) {
-        const int c = t;
-        for (int i = 0; i < NB; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int j = c; j < i; ++j) s = __builtin_fma(-a[i][j], x[j][c], s);
-            x[i][c] = i >= c ? s / a[i][i] : 0.0;
+        const double sd = sqrt(d);
+        const double lij = i > j ? r[j] / sd : 0.0;
+        r[j] = i > j ? lij : (i == j ? sd : 0.0);
+        if (j + 1 < NB) {
+            col[i] = lij;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int c = j + 1; c < NB; ++c) r[c] = __builtin_fma(-lij, col[c], r[c]);
+            __builtin_amdgcn_wave_barrier();
         }
     }
-    __syncthreads();
-    for (int e = t; e < NB * NB; e += 256) {
-        int r = e / NB, c = e % NB;
-        if (c <= r) A[(k0 + r) * lda + k0 + c] = a[r][c];
-        Linv[r * NB + c] = x[r][c];
-    }
+    if (sing && i == 0) *bad = 1;
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+        if (c <= i) ar[c] = r[c];
 }
 
 // acc(64x64, this wave's 32x32 quarter) = Ablk(64x64) * Bblk(64x64)^T from LDS via FP64 MFMA.
@@ -132,31 +132,29 @@ __device__ __forceinline__ void tile_abt(const double (*Ab)[NB + 1], const doubl
     }
 }
 
-// Panel: L_ik = A_ik inv(L_kk)^T for every row block i below k.
-__global__ __launch_bounds__(256) void c_panel(double *A, int64_t lda, int64_t k0, const double *Linv)
+// Panel: L_ik = A_ik L_kk^-T for every row block i below k. One wave per row block, lane r holds
+// row r of A_ik and solves x L_kk^T = a by columns (x_m = a_m / L_mm, then a_j -= x_m L_jm for
+// j > m), with L_kk in LDS read as broadcasts.
+__global__ __launch_bounds__(NB) void c_panel(double *A, int64_t lda, int64_t k0)
 {
-    __shared__ double ab[NB][NB + 1];
-    __shared__ double bb[NB][NB + 1];
+    __shared__ double L[NB][NB + 1];
+    const int t = threadIdx.x;
+    for (int r = 0; r < NB; ++r) L[r][t] = t <= r ? A[(k0 + r) * lda + k0 + t] : 0.0;
     const int64_t i0 = k0 + NB * (1 + (int64_t)blockIdx.x);
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-        int r = e / NB, c = e % NB;
-        ab[r][c] = A[(i0 + r) * lda + k0 + c];
-        bb[r][c] = Linv[r * NB + c];
-    }
+    double *ar = A + (i0 + t) * lda + k0;
+    double a[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) a[c] = ar[c];
     __syncthreads();
-    d4 acc[2][2];
-    tile_abt(ab, bb, acc);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+    for (int m = 0; m < NB; ++m) {
+        const double x = a[m] / L[m][m];
+        a[m] = x;
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
+        for (int j = m + 1; j < NB; ++j) a[j] = __builtin_fma(-x, L[j][m], a[j]);
+    }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int row = r0 + r * 16 + (lane >> 4) + 4 * v, col = c0 + c * 16 + (lane & 15);
-                A[(i0 + row) * lda + k0 + col] = acc[r][c][v];
-            }
+    for (int c = 0; c < NB; ++c) ar[c] = a[c];
 }
 
 // Trailing update A_ij -= L_ik L_jk^T over the lower block triangle j <= i below block k.
@@ -212,8 +210,10 @@ __global__ __launch_bounds__(256) void c_fwd(const double *A, int64_t lda, doubl
         double rhs[DIM];
         for (int k = 0; k < DIM; ++k) rhs[k] = yb[k][j];
         for (int i = 0; i < nb; ++i) {
+            // x_i from lane i's finished right-hand side, the same value in every lane
+            const double lii = Lb[i][i];
             double xi[DIM];
-            for (int k = 0; k < DIM; ++k) xi[k] = __shfl(rhs[k] / Lb[i][i], i, 64);
+            for (int k = 0; k < DIM; ++k) xi[k] = lane_value(rhs[k], i) / lii;
             if (j > i)
                 for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[j][i], xi[k], rhs[k]);
             if (j == i)
@@ -256,8 +256,9 @@ __global__ __launch_bounds__(256) void c_bwd(const double *A, int64_t lda, doubl
         double rhs[DIM];
         for (int k = 0; k < DIM; ++k) rhs[k] = xb[k][j];
         for (int i = nb - 1; i >= 0; --i) {
+            const double lii = Lb[i][i];
             double xi[DIM];
-            for (int k = 0; k < DIM; ++k) xi[k] = __shfl(rhs[k] / Lb[i][i], i, 64);
+            for (int k = 0; k < DIM; ++k) xi[k] = lane_value(rhs[k], i) / lii;
             if (j < i)
                 for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[i][j], xi[k], rhs[k]);
             if (j == i)
@@ -286,9 +287,8 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
     Pool *pool = ctx->pool.get();
     const int64_t lda = ((n + NB - 1) / NB) * NB;
     const int64_t nblk = lda / NB;
-    DevBuf bA, bInv, bFlag, bW, bY;
+    DevBuf bA, bFlag, bW, bY;
     RBF_TRY(bA.get(pool, sizeof(double) * (size_t)lda * (size_t)lda));
-    RBF_TRY(bInv.get(pool, sizeof(double) * NB * NB));
     RBF_TRY(bFlag.get(pool, sizeof(int32_t)));
     RBF_TRY(bW.get(pool, sizeof(double) * DIM * (size_t)n));
     RBF_TRY(bY.get(pool, sizeof(double) * DIM * (size_t)n));
@@ -298,9 +298,9 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
                        xc, n, lda, 1.0 / radius, basis, A);
     for (int64_t kb = 0; kb < nblk; ++kb) {
         const int64_t k0 = kb * NB, rest = nblk - kb - 1;
-        hipLaunchKernelGGL(c_diag, dim3(1), dim3(256), 0, s, A, lda, k0, bInv.as<double>(), bFlag.as<int32_t>());
+        hipLaunchKernelGGL(c_diag, dim3(1), dim3(NB), 0, s, A, lda, k0, bFlag.as<int32_t>());
         if (rest > 0) {
-            hipLaunchKernelGGL(c_panel, dim3((unsigned)rest), dim3(256), 0, s, A, lda, k0, bInv.as<const double>());
+            hipLaunchKernelGGL(c_panel, dim3((unsigned)rest), dim3(NB), 0, s, A, lda, k0);
             hipLaunchKernelGGL(c_trailing, dim3((unsigned)(rest * (rest + 1) / 2)), dim3(256), 0, s, A, lda,
                                k0, rest);
         }
