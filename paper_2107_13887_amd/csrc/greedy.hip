@@ -15,12 +15,12 @@
 // back substitution L^T alpha = y, and the level residual dS_{l+1} = dS_l - Phi_sC alpha is then
 // recomputed from alpha by the FP64 kernel sum (the same quantity the paper's loop produces).
 //
-// Execution. An iteration is a select phase (one workgroup: argmax of the per-tile maxima, stop
-// tests, row extraction, pivot) and an update phase (all workgroups, 64 surface points per tile:
-// new column, error update, tile argmax). On small surfaces a level runs as one persistent
-// cooperative kernel whose last workgroup to arrive at a barrier runs the select phase, so an
-// iteration costs one barrier; on large surfaces (or when a cooperative launch is impossible) the
-// two phases run as two kernel launches per iteration.
+// Execution. An iteration is a select phase (argmax of the per-tile maxima, stop tests, row
+// extraction, pivot) and an update phase (all workgroups, 64 surface points per tile: new column,
+// error update, tile argmax). On small surfaces a level runs as one persistent cooperative kernel
+// in which every workgroup runs the select phase itself after the iteration's one grid barrier,
+// keeping the Newton row in LDS for its update; on large surfaces (or when a cooperative launch is
+// impossible) the two phases run as two kernel launches per iteration.
 // Reductions run in a fixed order; squared norms are formed without fused multiply-adds so they
 // equal the textbook formula term by term.
 #include <hip/hip_cooperative_groups.h>
@@ -50,6 +50,7 @@ struct GState {
     int64_t n_iter;   // argmax selections made in this call (all levels)
     int32_t go;       // 1: an update for column n is pending
     int32_t stop;     // RBF_STOP_* once the level stopped, else -1
+    int32_t fault;    // 1: a persistent workgroup gave up waiting at a barrier
     double d;         // pivot of the pending column
     double c[3];      // Newton coefficients of the pending column
     double target2;   // squared tolerance of the level
@@ -75,6 +76,8 @@ struct GArgs {
     double *E;           // [DIM][n_s] current error
     uint8_t *sel;        // [n_s] selected in this level
     Cand *part;          // [g] per-tile maxima
+    double *E2;          // persistent form: second error buffer (iterations alternate)
+    Cand *part2;         // persistent form: second buffer of per-tile maxima
     int64_t g;           // number of tiles
     int64_t *ctrl;       // this level's slice of the output control list
     double *hist;
@@ -90,7 +93,7 @@ struct SelShared {
     double red[UWAVES];
     int32_t stop, skip;
     int64_t n, p;
-    double m2;
+    double m2, d, c[3];
 };
 
 struct UpdShared {
@@ -456,71 +459,276 @@ __global__ __launch_bounds__(NT) void g_level(GArgs a)
     }
 }
 
-// ---- persistent form with one barrier per iteration ------------------------------------------
-// Generation barrier in device memory (zeroed before launch). The last workgroup to arrive runs
-// the select phase for the next iteration before it releases the others, so an iteration costs
-// one arrival/release instead of two full barriers. Every workgroup executes the same number of
-// barriers: the exit test reads the state published by the release.
+// ---- persistent form: one barrier per iteration, the select phase in every workgroup ---------
+// Iteration it: update(it) applies the column appended by select(it - 1) to this workgroup's
+// tiles, then a grid barrier, then select(it) runs in every workgroup on the same data with the
+// same fixed-order reductions, so all of them take the same decisions and leave at the same
+// iteration; workgroup 0 alone writes the outputs. A workgroup may start update(it + 1) while
+// another still runs select(it), so what select(it) reads is never written by update(it + 1):
+// the error E and the per-tile maxima alternate between two buffers by iteration parity, the
+// Newton row is read from columns below n (update(it + 1) writes column n), and the update
+// excludes the point just selected by its own copy of p rather than through sel[].
 struct GridBar {
-    unsigned int count;
-    unsigned int gen;
+    unsigned int count;   // arrivals so far (all iterations); zeroed before the launch
+    unsigned int pad;
 };
+
+// Bound on the polls of one barrier (each after a short sleep): far beyond any iteration, it only
+// ends a wait that could never be met, with a fault flag instead of a hang.
+constexpr unsigned long long LEAN_SPIN_LIMIT = 1ull << 22;
+
+template <int DIM>
+__device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_t p, double d,
+                                 const double (&c)[DIM], bool row_in_lds, const double *Ein, double *Eout,
+                                 Cand *part_out, UpdShared &u)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i = tile * UPB + lane;
+    const bool ok = i < a.n_s;
+    const double *vt = a.V + tile * a.ldt * UPB + lane;
+    const double *prow = a.V + (p / UPB) * a.ldt * UPB + (p % UPB);   // V(p, j) at prow[j UPB]
+
+    double s = 0.0;
+    for (int64_t j0 = 0; j0 < n; j0 += LCHUNK) {
+        const int nj = (int)min<int64_t>(LCHUNK, n - j0);
+        if (!row_in_lds) {
+            __syncthreads();
+            for (int t = threadIdx.x; t < nj; t += NT) u.lsh[t] = prow[(j0 + t) * UPB];
+            __syncthreads();
+        }
+        const int per = (nj + UWAVES - 1) / UWAVES;
+        const int jb = w * per, je = min(nj, jb + per);
+        const double *col = vt + (j0 + jb) * UPB;
+        int j = jb;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (; j + 16 <= je; j += 16, col += 16 * UPB) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = col[q * UPB];
+#pragma unroll
+            for (int q = 0; q < 16; q += 4) {
+                s0 = __builtin_fma(v[q], u.lsh[j + q], s0);
+                s1 = __builtin_fma(v[q + 1], u.lsh[j + q + 1], s1);
+                s2 = __builtin_fma(v[q + 2], u.lsh[j + q + 2], s2);
+                s3 = __builtin_fma(v[q + 3], u.lsh[j + q + 3], s3);
+            }
+        }
+        for (; j + 4 <= je; j += 4, col += 4 * UPB) {
+            s0 = __builtin_fma(col[0], u.lsh[j], s0);
+            s1 = __builtin_fma(col[UPB], u.lsh[j + 1], s1);
+            s2 = __builtin_fma(col[2 * UPB], u.lsh[j + 2], s2);
+            s3 = __builtin_fma(col[3 * UPB], u.lsh[j + 3], s3);
+        }
+        for (; j < je; ++j, col += UPB) s0 = __builtin_fma(col[0], u.lsh[j], s0);
+        s += (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();                                    // psum of the previous tile has been read
+    u.psum[w][lane] = s;
+    __syncthreads();
+    if (w == 0) {
+        double m2 = -1.0;
+        int64_t idx = -1;
+        if (ok) {
+            double dot = u.psum[0][lane];
+#pragma unroll
+            for (int k = 1; k < UWAVES; ++k) dot += u.psum[k][lane];
+            const double v = (phi_pair<DIM>(a.xs, a.n_s, i, p, a.R, a.basis) - dot) / d;
+            a.V[(tile * a.ldt + n) * UPB + lane] = v;
+            double e[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                e[k] = __builtin_fma(-c[k], v, Ein[k * a.n_s + i]);
+                Eout[k * a.n_s + i] = e[k];
+            }
+            if (i != p && !a.sel[i]) {
+#pragma clang fp contract(off)
+                double q = e[0] * e[0];
+#pragma unroll
+                for (int k = 1; k < DIM; ++k) q = q + e[k] * e[k];
+                m2 = q;
+                idx = i;
+            }
+        }
+        wave_argmax(m2, idx);
+        if (lane == 0) part_out[tile] = Cand{m2, idx};
+    }
+}
+
+// The select phase of the persistent form, run by every workgroup on the state after the
+// barrier: the next point (argmax of the per-tile maxima, or a forced seed), the stop tests, the
+// Newton row l = V[p, 0:n] (kept in LDS for the update when it fits), the pivot and the Newton
+// coefficients. Workgroup 0 writes the outputs. Returns false when the level stops.
+template <int DIM>
+__device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double target2, int64_t &n_iter,
+                            const double *Ecur, const Cand *part, SelShared &s, UpdShared &u,
+                            int64_t &p_out, double &d_out, double (&c_out)[DIM])
+{
+    GState *st = a.st;
+    const bool writer = blockIdx.x == 0;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (forced < 0) {
+        double bm = -1.0;
+        int64_t bi = -1;
+        for (int64_t b = threadIdx.x; b < a.g; b += NT) {
+            const Cand c = part[b];
+            if (better(c.m2, c.idx, bm, bi)) {
+                bm = c.m2;
+                bi = c.idx;
+            }
+        }
+        wave_argmax(bm, bi);
+        if (lane == 0) s.sh[w] = Cand{bm, bi};
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m2 = 0.0;
+        int64_t p = forced;
+        if (forced < 0) {
+            m2 = s.sh[0].m2;
+            p = s.sh[0].idx;
+            for (int k = 1; k < UWAVES; ++k)
+                if (better(s.sh[k].m2, s.sh[k].idx, m2, p)) {
+                    m2 = s.sh[k].m2;
+                    p = s.sh[k].idx;
+                }
+        }
+        int32_t stop = -1;
+        if (forced < 0) {
+            if (p < 0) stop = RBF_STOP_ALL_SELECTED;
+            else if (m2 < target2) stop = RBF_STOP_EPS;
+        }
+        if (stop < 0 && n >= a.cap_level) stop = RBF_STOP_CAP;
+        s.stop = stop;
+        s.p = p;
+        s.m2 = m2;
+    }
+    __syncthreads();
+    if (s.stop >= 0) {
+        if (writer && threadIdx.x == 0) {
+            st->n = n;
+            st->go = 0;
+            st->n_iter = n_iter;
+            st->stop = s.stop;
+        }
+        return false;
+    }
+    const int64_t p = s.p;
+    double *row = a.Lpack + (n * (n + 1)) / 2;
+    double ep[DIM];
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) ep[k] = Ecur[k * a.n_s + p];
+    const double *prow = a.V + (p / UPB) * a.ldt * UPB + (p % UPB);
+    double part_ll = 0.0;
+    for (int64_t j = threadIdx.x; j < n; j += NT) {
+        const double v = prow[j * UPB];
+        if (j < LCHUNK) u.lsh[j] = v;
+        if (writer) row[j] = v;
+        part_ll = __builtin_fma(v, v, part_ll);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part_ll += __shfl_xor(part_ll, off, 64);
+    if (lane == 0) s.red[w] = part_ll;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ll = s.red[0];
+        for (int k = 1; k < UWAVES; ++k) ll += s.red[k];
+        const double d2 = 1.0 - ll;       // phi(0) - l.l
+        // l.l carries about (n + 1) ulps of rounding: a pivot below that is zero (breakdown).
+        if (!(d2 > (double)(n + 1) * 0x1p-52)) {
+            s.stop = RBF_STOP_BREAKDOWN;
+            if (writer) {
+                st->n = n;
+                st->go = 0;
+                st->n_iter = n_iter;
+                st->stop = RBF_STOP_BREAKDOWN;
+            }
+        } else {
+            const double d = sqrt(d2);
+            s.d = d;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) s.c[k] = ep[k] / d;
+            if (writer) {
+                row[n] = d;
+                st->p = p;
+                st->d = d;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    st->c[k] = s.c[k];
+                    a.coef[k * a.ld_coef + n] = s.c[k];
+                }
+                a.ctrl[n] = p;
+                a.sel[p] = 1;
+                if (forced < 0) {
+                    if (n_iter < a.hist_cap) a.hist[n_iter] = sqrt(s.m2);
+                    n_iter += 1;
+                }
+                st->n = n;
+                st->n_iter = n_iter;
+                st->go = 1;
+            }
+        }
+    }
+    __syncthreads();
+    if (s.stop >= 0) return false;
+    p_out = p;
+    d_out = s.d;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) c_out[k] = s.c[k];
+    return true;
+}
 
 template <int DIM>
 __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
 {
     __shared__ SelShared s;
     __shared__ UpdShared u;
-    __shared__ int32_t go_sh, last_sh;
-    __shared__ int64_t n_sh, p_sh;
-    __shared__ double d_sh, c_sh[3];
+    __shared__ int32_t abort_sh;
     const unsigned int nb = gridDim.x;
-    for (int64_t it = 0; it < a.max_iter; ++it) {
-        if (it > 0) {
-            for (int64_t t = blockIdx.x; t < a.g; t += nb) {
-                double c[DIM];
+    // Level state, read before this workgroup's first arrival: workgroup 0 writes it only after
+    // every workgroup has arrived.
+    int64_t n = a.st->n;
+    int64_t n_iter = a.st->n_iter;
+    const double target2 = a.st->target2;
+    bool pending = false;
+    int64_t p = -1;
+    double d = 1.0, c[DIM];
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) c[k] = c_sh[k];
-                update_tile<DIM>(a, t, n_sh, p_sh, d_sh, c, u);
-            }
+    for (int k = 0; k < DIM; ++k) c[k] = 0.0;
+    double *Eb[2] = {a.E, a.E2};
+    Cand *Pb[2] = {a.part, a.part2};
+    for (int64_t it = 0; it < a.max_iter; ++it) {
+        const int par = (int)(it & 1);
+        if (pending) {
+            const bool row_in_lds = n <= LCHUNK;
+            for (int64_t t = blockIdx.x; t < a.g; t += nb)
+                update_tile_lean<DIM>(a, t, n, p, d, c, row_in_lds, Eb[par ^ 1], Eb[par], Pb[par], u);
+            n += 1;
+            pending = false;
         }
-        // Arrive: the workgroup barrier orders this workgroup's stores, one release by thread 0
-        // publishes them device-wide. The last arriver acquires, selects, then releases the
-        // others, which poll the generation with relaxed loads and acquire once.
+        // Grid barrier: one release per arrival, relaxed polls of the arrival count, one acquire.
         __syncthreads();
-        unsigned int g0 = 0;
         if (threadIdx.x == 0) {
-            g0 = __hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned int arrived =
-                __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            last_sh = arrived == nb - 1;
-            if (last_sh) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        __syncthreads();
-        if (last_sh) {
-            const int64_t k = it;   // selection number within the level (seeds first)
-            select_phase<DIM>(a, k < a.n_seeds ? a.seeds[k] : -1, s);
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        } else if (threadIdx.x == 0) {
-            while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g0)
+            __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned int target = nb * (unsigned int)(it + 1);
+            unsigned long long spins = 0;
+            int32_t ab = 0;
+            while (__hip_atomic_load(&bar->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 __builtin_amdgcn_s_sleep(1);
+                if (++spins > LEAN_SPIN_LIMIT) {
+                    ab = 1;
+                    break;
+                }
+            }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            abort_sh = ab;
+            if (ab) __hip_atomic_store(&a.st->fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const GState *st = a.st;
-            go_sh = __hip_atomic_load(&st->go, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            n_sh = st->n;
-            p_sh = st->p;
-            d_sh = st->d;
-            for (int k = 0; k < DIM; ++k) c_sh[k] = st->c[k];
-        }
-        __syncthreads();
-        if (!go_sh) break;
+        if (abort_sh) return;
+        const int64_t forced = it < a.n_seeds ? a.seeds[it] : -1;
+        if (!select_lean<DIM>(a, forced, n, target2, n_iter, Eb[par], Pb[par], s, u, p, d, c)) break;
+        pending = true;
     }
 }
 
@@ -870,8 +1078,12 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     const int coop_max = mode == 2 ? 0
                        : cooperative_blocks(mode == 0 ? (const void *)g_level_lean<DIM> : (const void *)g_level<DIM>,
                                             ctx->n_cu);
-    DevBuf bBar;
+    DevBuf bBar, bE2, bPart2;
     RBF_TRY(bBar.get(pool, sizeof(GridBar)));
+    if (mode == 0 && coop_max > 0) {
+        RBF_TRY(bE2.get(pool, sizeof(double) * DIM * (size_t)n_s));
+        RBF_TRY(bPart2.get(pool, sizeof(Cand) * (size_t)g));
+    }
     GArgs a{};
     a.st = st;
     a.xs = xs;
@@ -885,6 +1097,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     a.E = bE.as<double>();
     a.sel = bSel.as<uint8_t>();
     a.part = bPart.as<Cand>();
+    a.E2 = bE2.as<double>();
+    a.part2 = bPart2.as<Cand>();
     a.g = g;
     a.hist = bHist.as<double>();
     a.hist_cap = cap;
@@ -963,6 +1177,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
             if (e == hipSuccess) {
                 RBF_HIP(hipMemcpyAsync(&hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
                 RBF_HIP(hipStreamSynchronize(s));
+                if (hs.fault)
+                    return fail(RBF_E_DEVICE, "greedy level %d: a workgroup of the persistent kernel timed out at a barrier", l);
                 if (hs.stop < 0)
                     return fail(RBF_E_DEVICE, "greedy level %d did not stop within %lld iterations", l,
                                 (long long)a.max_iter);

@@ -438,7 +438,8 @@ uint64_t greedy_footprint(int dim, int64_t n_s, int64_t cap)
     return sizeof(double) * (2 * ((cols + 1) * rows + cols * (cols + 1) / 2) + (uint64_t)(3 * dim + 1) * n_s +
                              (uint64_t)(dim + 1) * cols + 2 * (uint64_t)cap) +
            (uint64_t)n_s * 17 + sizeof(int64_t) * (uint64_t)cap + sizeof(double) * (uint64_t)cap * 2 * dim +
-           sizeof(double) * ((uint64_t)dim * n_s + (uint64_t)n_s / 256 + 1);   // FP32 error check
+           sizeof(double) * ((uint64_t)dim * n_s + (uint64_t)n_s / 256 + 1) +   // FP32 error check
+           sizeof(double) * (uint64_t)dim * n_s + 16 * (uint64_t)(n_s / 64 + 1);  // persistent form's second buffers
 }
 
 }  // namespace
