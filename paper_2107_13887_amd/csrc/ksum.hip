@@ -140,13 +140,16 @@ __device__ __forceinline__ void level_accum(const KArgs &a, int l, const double 
     constexpr int ST = 2 * DIM;
     constexpr int AOFF = DIM;
     const double inv_r = a.lv[l].inv_r;
+    // Four independent pairs in flight per lane with one point per lane (small launches, where
+    // the last waves of a compute unit run alone), two with two points per lane.
+    constexpr int UNR = P == 1 ? 4 : 2;
     if (MIXED && a.lv[l].fp32) {
         float q32[P][DIM];
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int k = 0; k < DIM; ++k) q32[p][k] = (float)((xq[p][k] - org[k]) * inv_r);
-#pragma unroll 2
+#pragma unroll UNR
         for (int c = c0; c < c1; ++c) {
             const double *cc = tile + c * ST;
             double cal[DIM];
@@ -169,7 +172,7 @@ __device__ __forceinline__ void level_accum(const KArgs &a, int l, const double 
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int k = 0; k < DIM; ++k) q64[p][k] = xq[p][k] * inv_r;
-#pragma unroll 2
+#pragma unroll UNR
         for (int c = c0; c < c1; ++c) {
             const double *cc = tile + c * ST;
             double cal[DIM], cpos[DIM];
