@@ -603,10 +603,26 @@ void launch_sum_b(const KArgs &a, dim3 grid, int P, bool mixed, int32_t basis, h
     }
 }
 
-int env_int(const char *name, int dflt)
+// Launch-shape overrides, read once per process (0: not set).
+struct ShapeEnv {
+    int P, blocks, max_split, split;
+    ShapeEnv()
+    {
+        auto get = [](const char *name) {
+            const char *v = getenv(name);
+            return v && *v ? atoi(v) : 0;
+        };
+        P = get("RBF_KSUM_P");
+        blocks = get("RBF_KSUM_BLOCKS");
+        max_split = get("RBF_KSUM_MAX_SPLIT");
+        split = get("RBF_KSUM_SPLIT");
+    }
+};
+
+const ShapeEnv &shape_env()
 {
-    const char *v = getenv(name);
-    return v && *v ? atoi(v) : dflt;
+    static const ShapeEnv e;
+    return e;
 }
 
 }  // namespace
@@ -670,15 +686,16 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     // Two points per lane share every control read from LDS; one point per lane gives twice the
     // workgroups, which balances better when there are few blocks (the cost of a block varies
     // with the number of controls near it).
-    int P = env_int("RBF_KSUM_P", n_rows < (int64_t)8 * ctx->n_cu * VBLOCK ? 1 : 2);
+    const ShapeEnv &env = shape_env();
+    int P = env.P ? env.P : (n_rows < (int64_t)8 * ctx->n_cu * VBLOCK ? 1 : 2);
     if (P != 1 && P != 2) P = 2;
     const int64_t nbx = (n_rows + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
-    const int64_t target = (int64_t)env_int("RBF_KSUM_BLOCKS", 8 * ctx->n_cu);
+    const int64_t target = env.blocks > 0 ? env.blocks : (int64_t)8 * ctx->n_cu;
     // Split only while every split keeps at least 128 controls: a split re-reads the points and
     // writes partial sums, which pays only when it turns a ragged last round of waves into many.
     int S = (int)std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, nc_max / 128));
-    S = std::min(S, env_int("RBF_KSUM_MAX_SPLIT", 64));
-    if (const char *e = getenv("RBF_KSUM_SPLIT")) S = std::max(1, atoi(e));
+    S = std::min(S, env.max_split > 0 ? env.max_split : 64);
+    if (env.split > 0) S = env.split;
     a.n_split = S;
     if (S > 1) {
         RBF_TRY(partial.get(ctx->pool.get(), sizeof(double) * (size_t)S * DIM * n_rows));

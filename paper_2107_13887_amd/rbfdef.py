@@ -35,6 +35,23 @@ def _precision(precision, n_levels: int):
     return RBF_FP64, (_i32 * n_levels)(*[code(p) for p in precision])
 
 
+_LEVEL_ARRAYS: dict = {}
+
+
+def _level_arrays(radius, D, level_off):
+    """ctypes copies of the per-level radii, support distances and offsets (cached by value)."""
+    key = (tuple(radius), tuple(D), tuple(level_off))
+    got = _LEVEL_ARRAYS.get(key)
+    if got is None:
+        nl = len(radius)
+        got = ((_f64 * nl)(*[float(x) for x in radius]), (_f64 * nl)(*[float(x) for x in D]),
+               (_i32 * (nl + 1))(*[int(x) for x in level_off]))
+        if len(_LEVEL_ARRAYS) > 256:
+            _LEVEL_ARRAYS.clear()
+        _LEVEL_ARRAYS[key] = got
+    return got
+
+
 def _basis(name: str) -> int:
     if name not in BASES:
         raise ValueError(f"unknown basis {name!r}; one of {sorted(BASES)}")
@@ -171,15 +188,19 @@ def _dev(t, name: str, dim: Optional[int] = None, n: Optional[int] = None, allow
         if n is not None and t.shape[0] != n:
             raise ValueError(f"{name} has {t.shape[0]} entries, expected {n}")
         return t.data_ptr(), t.shape[0]
-    if t.dim() != 2:
+    shape, stride = t.shape, t.stride()
+    if len(shape) != 2:
         raise ValueError(f"{name} must be [dim, n]")
-    if dim is not None and t.shape[0] != dim:
-        raise ValueError(f"{name} has {t.shape[0]} rows, expected {dim}")
-    if n is not None and t.shape[1] != n:
-        raise ValueError(f"{name} has {t.shape[1]} columns, expected {n}")
-    if t.stride(1) != 1 or (not allow_ld and not t.is_contiguous()):
+    if dim is not None and shape[0] != dim:
+        raise ValueError(f"{name} has {shape[0]} rows, expected {dim}")
+    if n is not None and shape[1] != n:
+        raise ValueError(f"{name} has {shape[1]} columns, expected {n}")
+    # Row-contiguous SoA: unit stride along a row; rows at the leading dimension stride[0], which
+    # must be the row length unless a larger leading dimension is allowed (no element: any).
+    if shape[0] and shape[1] and ((shape[1] > 1 and stride[1] != 1) or stride[0] < shape[1] or
+                                  (not allow_ld and shape[0] > 1 and stride[0] != shape[1])):
         raise ValueError(f"{name} must be row-contiguous SoA")
-    return t.data_ptr(), t.stride(0)
+    return t.data_ptr(), stride[0]
 
 
 # ---- context -------------------------------------------------------------------------------------
@@ -423,9 +444,7 @@ def rbf_geom_volume_update(ctx: int, geom: int, radius: Sequence[float], D: Sequ
     if int(level_off[-1]) > xc.shape[1]:
         raise ValueError("level_off exceeds the control arrays")
     pdv, _ = _dev(dv, "dv", dim, None)
-    r = (_f64 * nl)(*[float(x) for x in radius])
-    d = (_f64 * nl)(*[float(x) for x in D])
-    off = (_i32 * (nl + 1))(*[int(x) for x in level_off])
+    r, d, off = _level_arrays(radius, D, level_off)
     prec, levels = _precision(precision, nl)
     _check(lib().rbf_geom_volume_update(ctx, geom, nl, r, d, off, ldc, pxc, pa, pdv, prec, levels,
                                         _basis(basis), _stream(stream)),
