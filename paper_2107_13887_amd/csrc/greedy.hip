@@ -78,6 +78,7 @@ struct GArgs {
     Cand *part;          // [g] per-tile maxima
     double *E2;          // persistent form: second error buffer (iterations alternate)
     Cand *part2;         // persistent form: second buffer of per-tile maxima
+    unsigned long long spin_limit;   // persistent form: polls of one barrier before giving up
     int64_t g;           // number of tiles
     int64_t *ctrl;       // this level's slice of the output control list
     double *hist;
@@ -473,8 +474,10 @@ struct GridBar {
     unsigned int pad;
 };
 
-// Bound on the polls of one barrier (each after a short sleep): far beyond any iteration, it only
-// ends a wait that could never be met, with a fault flag instead of a hang.
+// Default bound on the polls of one barrier (each after a short sleep, about 4 s in all): far
+// beyond any iteration, it only ends a wait that could never be met, with a fault flag instead of
+// a hang. RBF_GREEDY_SPIN_LIMIT overrides it (0: give up at the first poll that finds the count
+// short, which makes the failure path testable).
 constexpr unsigned long long LEAN_SPIN_LIMIT = 1ull << 22;
 
 template <int DIM>
@@ -714,11 +717,11 @@ __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
             unsigned long long spins = 0;
             int32_t ab = 0;
             while (__hip_atomic_load(&bar->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > LEAN_SPIN_LIMIT) {
+                if (spins++ >= a.spin_limit) {
                     ab = 1;
                     break;
                 }
+                __builtin_amdgcn_s_sleep(1);
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             abort_sh = ab;
@@ -1099,6 +1102,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     a.part = bPart.as<Cand>();
     a.E2 = bE2.as<double>();
     a.part2 = bPart2.as<Cand>();
+    a.spin_limit = LEAN_SPIN_LIMIT;
+    if (const char *e = getenv("RBF_GREEDY_SPIN_LIMIT")) a.spin_limit = strtoull(e, nullptr, 10);
     a.g = g;
     a.hist = bHist.as<double>();
     a.hist_cap = cap;

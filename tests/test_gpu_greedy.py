@@ -151,3 +151,19 @@ def test_weight_solve_not_spd(gctx):
     with pytest.raises(rbfdef.RbfError) as e:
         rbfdef.rbf_solve_weights(gctx, 1.0, to_dev(xc), to_dev(np.zeros((2, 3))))
     assert e.value.status == rbfdef.RBF_E_NOT_SPD
+
+
+def test_persistent_barrier_timeout_is_a_device_error(gctx, orc, monkeypatch):
+    """A barrier of the persistent greedy kernel that gives up waiting ends the call with
+    RBF_E_DEVICE instead of hanging. Forced from the host with a zero poll limit on the kernel's
+    own bounded wait (every workgroup still exits); the next call on the same context is normal."""
+    w = synth.workload_cfg0()           # 7 tiles: the persistent form, several workgroups
+    xs, ds = to_dev(w.xs), to_dev(w.ds)
+    monkeypatch.setenv("RBF_GREEDY_SPIN_LIMIT", "0")
+    with pytest.raises(rbfdef.RbfError) as err:
+        rbfdef.rbf_greedy_select(gctx, xs, ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds)
+    assert err.value.status == rbfdef.RBF_E_DEVICE
+    assert "timed out" in str(err.value)
+    monkeypatch.delenv("RBF_GREEDY_SPIN_LIMIT")
+    ref, cs = _greedy_both(gctx, orc, w)
+    _check_same(orc, w, ref, cs)
