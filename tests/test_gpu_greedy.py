@@ -167,3 +167,25 @@ def test_persistent_barrier_timeout_is_a_device_error(gctx, orc, monkeypatch):
     monkeypatch.delenv("RBF_GREEDY_SPIN_LIMIT")
     ref, cs = _greedy_both(gctx, orc, w)
     _check_same(orc, w, ref, cs)
+
+
+_LONG_LEVEL = {}
+
+
+@pytest.mark.parametrize("mode", ["lean", "kernels"])
+def test_greedy_level_longer_than_one_lds_row(gctx, orc, monkeypatch, mode):
+    """A level of more columns (2150) than one LDS pass of the Newton row holds (2048): the update
+    stages the row from the basis in chunks. Same selections, residual and weights as the oracle,
+    in the persistent schedule and in the two-launch one."""
+    w = synth.random_workload(11, 2, 2400, 10, [0.05], 0.0, cap=2150)
+    if "ref" not in _LONG_LEVEL:
+        _LONG_LEVEL["ref"] = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
+                                        seeds=w.seeds)
+    ref = _LONG_LEVEL["ref"]
+    monkeypatch.setenv("RBF_GREEDY_MODE", mode)
+    print(f"case {w.name} cap {w.cap_total()} schedule {mode}", flush=True)
+    cs = rbfdef.rbf_greedy_select(gctx, to_dev(w.xs), to_dev(w.ds), w.radius, w.eps, rho=w.rho,
+                                  cap=w.cap_total(), seeds=w.seeds)
+    torch.cuda.synchronize()
+    assert cs.total == 2150 and cs.level_stop[0] == rbfdef.RBF_STOP_CAP
+    _check_same(orc, w, ref, cs)
