@@ -248,6 +248,29 @@ def _median_ms(stream, fn, reps):
     return statistics.median(a_.elapsed_time(b_) for a_, b_ in evs)
 
 
+def error_curve(cs, w, points=40):
+    """The greedy's normalized error max ||E|| / max ||dS|| before each argmax selection,
+    subsampled, with the iteration index and an elapsed time from each level's wall time spread
+    evenly over its iterations (the error-versus-time curve of Section 3)."""
+    import numpy as np
+
+    hist = cs.err_hist.cpu().numpy() if cs.err_hist is not None else np.zeros(0)
+    if hist.size == 0:
+        return []
+    scale = float(np.sqrt((w.ds ** 2).sum(0)).max())
+    t = np.zeros(hist.size)
+    start, clock = 0, 0.0
+    for l in range(cs.n_levels_used):
+        n_l = cs.level_off[l + 1] - cs.level_off[l] - (len(w.seeds[l]) if l < len(w.seeds) else 0)
+        n_l = max(0, min(n_l, hist.size - start))
+        if n_l:
+            t[start:start + n_l] = clock + cs.level_seconds[l] * (np.arange(n_l) + 1) / n_l
+        start += n_l
+        clock += cs.level_seconds[l]
+    pick = np.unique(np.linspace(0, hist.size - 1, min(points, hist.size)).round().astype(int))
+    return [[int(i), float(t[i]), float(hist[i] / scale)] for i in pick]
+
+
 def _normwise(got, ref):
     import numpy as np
 
@@ -492,6 +515,7 @@ def main():
                             "work_unit": "Newton-basis stream of every iteration (N_s x n read, one "
                                          "column written, E and x_s), whole greedy call timed"},
         "greedy_iteration_floor_us": floor_us,
+        "greedy_error_curve": error_curve(cs, w),
         "dense_solve": dense,
         "greedy_levels": [{"controls": n_c[l] if l < len(n_c) else 0, "seconds": cs.level_seconds[l],
                            "max_err_in": cs.level_in_max[l], "max_err_out": cs.level_max_err[l]}

@@ -138,6 +138,10 @@ typedef struct {
                                               over the surface, the error of level l's interpolant
                                               with FP32 pair arithmetic against FP64; 0 otherwise */
     int64_t n_iterations;                  /* out: argmax selections made (seeds excluded) */
+    double *err_hist;                      /* device [capacity] or NULL: max_i ||E_i|| over the
+                                              candidates before each argmax selection, in order
+                                              over the levels (the greedy error curve of
+                                              section 3); n_iterations entries are written */
 } rbf_ctrl_set;
 
 /* Multi-level greedy surface point selection, Section 3. Per level l: start from the residual

@@ -1316,6 +1316,9 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     out->n_iterations = hs.n_iter;
     if (out->e_final)
         RBF_HIP(hipMemcpyAsync(out->e_final, R, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
+    if (out->err_hist && hs.n_iter > 0)
+        RBF_HIP(hipMemcpyAsync(out->err_hist, bHist.ptr, sizeof(double) * (size_t)std::min<int64_t>(hs.n_iter, cap),
+                               hipMemcpyDeviceToDevice, s));
     RBF_HIP(hipStreamSynchronize(s));
     bool cap_hit = false, brk = false;
     for (int l = 0; l < used; ++l) {

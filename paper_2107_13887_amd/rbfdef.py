@@ -78,7 +78,7 @@ class rbf_ctrl_set(ctypes.Structure):
                 ("level_off", _i32 * (MAX_LEVELS + 1)), ("level_stop", _i32 * MAX_LEVELS),
                 ("level_max_err", _f64 * MAX_LEVELS), ("level_in_max", _f64 * MAX_LEVELS),
                 ("level_seconds", _f64 * MAX_LEVELS), ("level_fp32_err", _f64 * MAX_LEVELS),
-                ("n_iterations", _i64)]
+                ("n_iterations", _i64), ("err_hist", _vp)]
 
 
 class rbf_request(ctypes.Structure):
@@ -264,6 +264,7 @@ class CtrlSet:
     level_in_max: List[float] = field(default_factory=list)    # max ||dS_l|| per level input
     level_seconds: List[float] = field(default_factory=list)
     level_fp32_err: List[float] = field(default_factory=list)   # FP32 error at the surface (mixed)
+    err_hist: object = None   # float64 [n_iterations]: max ||E|| before each argmax selection
 
     def fp32_levels(self, tol: float = 1e-6) -> List[bool]:
         """Levels whose measured FP32 error is at most tol max ||dS|| (the serving path's rule)."""
@@ -326,12 +327,14 @@ def rbf_greedy_select(ctx: int, xs, ds, radius: Sequence[float], eps: float, rho
     xc = torch.zeros((dim, capacity), dtype=torch.float64, device=dev)
     alpha = torch.zeros((dim, capacity), dtype=torch.float64, device=dev)
     ef = torch.zeros((dim, n_s), dtype=torch.float64, device=dev) if want_residual else None
+    hist = torch.zeros((capacity,), dtype=torch.float64, device=dev)
     out = rbf_ctrl_set()
     out.capacity = capacity
     out.ctrl_idx = ctrl.data_ptr()
     out.xc = xc.data_ptr()
     out.alpha = alpha.data_ptr()
     out.e_final = ef.data_ptr() if ef is not None else None
+    out.err_hist = hist.data_ptr()
     st = _check(lib().rbf_greedy_select(ctx, ctypes.byref(p), n_s, pxs, pds, ctypes.byref(out),
                                         _stream(stream)), "rbf_greedy_select")
     del keep
@@ -343,7 +346,8 @@ def rbf_greedy_select(ctx: int, xs, ds, radius: Sequence[float], eps: float, rho
                    n_levels_used=nl, n_iterations=out.n_iterations, status=st,
                    level_in_max=[out.level_in_max[l] for l in range(len(radius))],
                    level_seconds=[out.level_seconds[l] for l in range(len(radius))],
-                   level_fp32_err=[out.level_fp32_err[l] for l in range(len(radius))])
+                   level_fp32_err=[out.level_fp32_err[l] for l in range(len(radius))],
+                   err_hist=hist[: out.n_iterations])
 
 
 def rbf_solve_weights(ctx: int, radius: float, xc, dsc, alpha=None, stream=None, basis: str = "c2"):

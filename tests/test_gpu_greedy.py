@@ -46,6 +46,10 @@ def _check_same(orc, w, ref, cs):
     assert np.array_equal(xc, w.xs[:, ref.ctrl_idx])
     for l in range(ref.n_levels_used):
         assert abs(cs.level_max_err[l] - ref.level_max_err[l]) <= tol
+    # the error curve: max ||E|| before each argmax selection
+    hist = cs.err_hist.cpu().numpy()
+    assert cs.n_iterations == len(ref.history) == hist.size
+    assert np.abs(hist - ref.history).max() <= tol
 
 
 @pytest.mark.parametrize("seed,dim,n_s,radius,eps", [
