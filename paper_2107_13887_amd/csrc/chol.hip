@@ -197,6 +197,7 @@ __global__ __launch_bounds__(256) void c_fwd(const double *A, int64_t lda, doubl
 {
     __shared__ double Lb[NB][NB + 1];
     __shared__ double yb[DIM][NB];
+    __shared__ double rinv[NB];                         // 1 / L[i][i], off the serial chain
     const int nb = (int)min<int64_t>(NB, n - b0);
     for (int e = threadIdx.x; e < NB * NB; e += 256) {
         int r = e / NB, c = e % NB;
@@ -205,15 +206,17 @@ __global__ __launch_bounds__(256) void c_fwd(const double *A, int64_t lda, doubl
     if (threadIdx.x < NB)
         for (int k = 0; k < DIM; ++k) yb[k][threadIdx.x] = threadIdx.x < nb ? b[k * ldb + b0 + threadIdx.x] : 0.0;
     __syncthreads();
+    if (threadIdx.x < NB) rinv[threadIdx.x] = 1.0 / Lb[threadIdx.x][threadIdx.x];
+    __syncthreads();
     if (threadIdx.x < NB) {
         const int j = threadIdx.x;
         double rhs[DIM];
         for (int k = 0; k < DIM; ++k) rhs[k] = yb[k][j];
         for (int i = 0; i < nb; ++i) {
             // x_i from lane i's finished right-hand side, the same value in every lane
-            const double lii = Lb[i][i];
+            const double ri = rinv[i];
             double xi[DIM];
-            for (int k = 0; k < DIM; ++k) xi[k] = lane_value(rhs[k], i) / lii;
+            for (int k = 0; k < DIM; ++k) xi[k] = lane_value(rhs[k], i) * ri;
             if (j > i)
                 for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[j][i], xi[k], rhs[k]);
             if (j == i)
@@ -243,6 +246,7 @@ __global__ __launch_bounds__(256) void c_bwd(const double *A, int64_t lda, doubl
 {
     __shared__ double Lb[NB][NB + 1];
     __shared__ double xb[DIM][NB];
+    __shared__ double rinv[NB];                         // 1 / L[i][i], off the serial chain
     const int nb = (int)(b1 - b0);
     for (int e = threadIdx.x; e < NB * NB; e += 256) {
         int r = e / NB, c = e % NB;
@@ -251,14 +255,16 @@ __global__ __launch_bounds__(256) void c_bwd(const double *A, int64_t lda, doubl
     if (threadIdx.x < NB)
         for (int k = 0; k < DIM; ++k) xb[k][threadIdx.x] = threadIdx.x < nb ? y[k * ldy + b0 + threadIdx.x] : 0.0;
     __syncthreads();
+    if (threadIdx.x < NB) rinv[threadIdx.x] = 1.0 / Lb[threadIdx.x][threadIdx.x];
+    __syncthreads();
     if (threadIdx.x < NB) {
         const int j = threadIdx.x;
         double rhs[DIM];
         for (int k = 0; k < DIM; ++k) rhs[k] = xb[k][j];
         for (int i = nb - 1; i >= 0; --i) {
-            const double lii = Lb[i][i];
+            const double ri = rinv[i];
             double xi[DIM];
-            for (int k = 0; k < DIM; ++k) xi[k] = lane_value(rhs[k], i) / lii;
+            for (int k = 0; k < DIM; ++k) xi[k] = lane_value(rhs[k], i) * ri;
             if (j < i)
                 for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[i][j], xi[k], rhs[k]);
             if (j == i)
