@@ -185,6 +185,7 @@ def serving_replay(ctx, geoms, reqs, time_scale=1.0, compare=True):
         g = geoms[r.geom]
         dss.append(torch.from_numpy(np.ascontiguousarray(g.shape * (r.step / steps))).to(dev))
     torch.cuda.synchronize()
+    log(f"bench: serving replay: {len(geoms)} geometries resident, {len(reqs)} requests to submit")
     pend = []
     t0 = rbfdef.rbf_now()
     for r, ds in zip(reqs, dss):
@@ -195,7 +196,11 @@ def serving_replay(ctx, geoms, reqs, time_scale=1.0, compare=True):
         pend.append(rbfdef.rbf_submit(ctx, handles[r.geom], ds, dvs[r.geom], g.radius, r.eps,
                                       [g.D] * len(g.radius), rho=0.1, cap=g.cap, precision=r.precision,
                                       warm_start=r.step > 1))
-    infos = [rbfdef.rbf_wait(ctx, q) for q in pend]
+    infos = []
+    for k, q in enumerate(pend):
+        infos.append(rbfdef.rbf_wait(ctx, q))
+        if (k + 1) % 32 == 0:
+            log(f"bench: serving replay: {k + 1}/{len(pend)} requests done")
     t_end = max(i.t_done for i in infos)
     failed = sum(1 for i in infos if i.state != rbfdef.REQ_DONE)
     lat = sorted((i.t_done - i.t_arrive) * 1e3 for i in infos)
@@ -221,7 +226,9 @@ def serving_replay(ctx, geoms, reqs, time_scale=1.0, compare=True):
                      torch.from_numpy(g.dwall).to(dev)) for g in geoms]
         torch.cuda.synchronize()
         c0 = time.perf_counter()
-        for r, ds in zip(reqs, dss):
+        for k, (r, ds) in enumerate(zip(reqs, dss)):
+            if k % 32 == 0:
+                log(f"bench: sequential plain FP64: request {k}/{len(reqs)}")
             g = geoms[r.geom]
             xs, xv, dw = dev_geom[r.geom]
             cs = rbfdef.rbf_greedy_select(ctx, xs, ds, g.radius, r.eps, rho=0.1, cap=g.cap,
@@ -566,7 +573,7 @@ def serve_main(args):
     from paper_2107_13887_amd import rbfdef
 
     t0 = time.perf_counter()
-    geoms, reqs = synth.serving_mix()
+    geoms, reqs = synth.serving_mix(progress=log)
     log(f"bench: serving mix built in {time.perf_counter() - t0:.1f}s")
     ctx = rbfdef.rbf_ctx_create(0)
     torch.cuda.synchronize()

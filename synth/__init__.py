@@ -452,13 +452,13 @@ class MixRequest:
 
 
 def serving_mix(n_geom: int = 64, steps: int = 4, rate: float = 20.0, frac_2d: float = 0.6,
-                scale: float = 1.0, precision: str = "mixed", seed: int = 4):
+                scale: float = 1.0, precision: str = "mixed", seed: int = 4, progress=None):
     """Seeded request mix: 2D airfoils (surface log-uniform in [500, 8000] points, O-mesh with
     40-100 layers) and 3D wings (400 x [25, 200] surface grid, 50 layers), each geometry deformed
     in `steps` successive icing steps of growing amplitude (ice horns, or bending plus twist for
     half of the wings), eps drawn from {1e-4, 1e-5}, Poisson arrivals at `rate` per second with
     each geometry's steps in order. `scale` < 1 shrinks every surface and volume (tests, quick
-    runs)."""
+    runs). progress (optional) is called with a line of text after each geometry."""
     rng = np.random.default_rng(SEED_BASE + seed)
     geoms: List[MixGeometry] = []
     n2 = int(round(frac_2d * n_geom))
@@ -498,6 +498,8 @@ def serving_mix(n_geom: int = 64, steps: int = 4, rate: float = 20.0, frac_2d: f
                 shape = bend_twist(xyz, yk[-1])
             geoms.append(MixGeometry(3, xyz, vol, wall_distance(xyz, vol), n, np.ascontiguousarray(shape),
                                      [3.0, 0.8, 0.2], 1.0, min(4000, xyz.shape[1])))
+        if progress is not None:
+            progress(f"serving mix: geometry {g + 1}/{n_geom} built ({geoms[-1].xv.shape[1]} volume points)")
     order = [g for g in range(n_geom) for _ in range(steps)]
     rng.shuffle(order)
     seen = [0] * n_geom
