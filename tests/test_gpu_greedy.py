@@ -193,3 +193,29 @@ def test_greedy_level_longer_than_one_lds_row(gctx, orc, monkeypatch, mode):
     torch.cuda.synchronize()
     assert cs.total == 2150 and cs.level_stop[0] == rbfdef.RBF_STOP_CAP
     _check_same(orc, w, ref, cs)
+
+
+@pytest.mark.parametrize("wgs", [1, 3])
+def test_greedy_persistent_with_several_tiles_per_workgroup(gctx, orc, monkeypatch, wgs):
+    """The persistent schedule with fewer workgroups than tiles (each updates several tiles per
+    iteration, reusing the Newton row it holds in LDS): the oracle's selections."""
+    monkeypatch.setenv("RBF_GREEDY_MODE", "lean")
+    monkeypatch.setenv("RBF_GREEDY_WGS", str(wgs))
+    w = synth.workload_cfg0()           # 7 tiles
+    ref, cs = _greedy_both(gctx, orc, w)
+    _check_same(orc, w, ref, cs)
+
+
+def test_greedy_long_level_with_several_tiles_per_workgroup(gctx, orc, monkeypatch):
+    """Several tiles per workgroup with a Newton row longer than one LDS pass: the row is staged
+    again from the basis for every tile."""
+    w = synth.random_workload(11, 2, 2400, 10, [0.05], 0.0, cap=2150)
+    if "ref" not in _LONG_LEVEL:
+        _LONG_LEVEL["ref"] = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
+                                        seeds=w.seeds)
+    monkeypatch.setenv("RBF_GREEDY_MODE", "lean")
+    monkeypatch.setenv("RBF_GREEDY_WGS", "5")
+    cs = rbfdef.rbf_greedy_select(gctx, to_dev(w.xs), to_dev(w.ds), w.radius, w.eps, rho=w.rho,
+                                  cap=w.cap_total(), seeds=w.seeds)
+    torch.cuda.synchronize()
+    _check_same(orc, w, _LONG_LEVEL["ref"], cs)
