@@ -78,10 +78,16 @@ def build_workload(name):
 
 
 def kernel_source_hash():
+    """Hash of the kernel-sum source with comments and white space removed, so that a counter
+    summary stays matched to its kernel through edits of the comments only."""
     import hashlib
+    import re
 
-    with open(os.path.join(ROOT, "paper_2107_13887_amd", "csrc", "ksum.hip"), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(os.path.join(ROOT, "paper_2107_13887_amd", "csrc", "ksum.hip")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return hashlib.sha256("".join(src.split()).encode()).hexdigest()[:16]
 
 
 def measured_traffic(workload, precision):

@@ -1,4 +1,4 @@
-// Wendland C2 kernel sums on gfx950: the volume update of eqs. (19)/(23) and the surface
+// Wendland kernel sums (Table 1) on gfx950: the volume update of eqs. (19)/(23) and the surface
 // interpolant/residual of eqs. (1)/(12).
 //
 //   out_k(p) = base_k(p) - sign * sum_l psi(d_p / D_l) sum_{c in level l} phi(||x_p - x_c|| / R_l) alpha_k,c
@@ -12,12 +12,14 @@
 //     same LDS address, a broadcast without bank conflicts;
 //   * the control list of each level may be split over gridDim.y so that few points still give
 //     enough waves; split partial sums are reduced in a fixed order (deterministic results);
-//   * compact support: each workgroup takes the bounding box of its points that any level
-//     weights, and while a control tile is staged every control whose distance to that box is at
-//     least R_l (with a relative margin of 1e-4) is dropped by a stable in-tile compaction, so
-//     the pair loop runs over the controls that can reach the workgroup only. Dropped pairs
-//     have phi = 0 exactly, and the order of the kept ones is unchanged, so the sums equal the
-//     uncut ones;
+//   * compact support: each workgroup takes a bounding box of its points (on a resident geometry
+//     the union of the stored boxes of its 64-row groups, otherwise the box of its points that
+//     each support distance weights), and while a control tile is staged every control whose
+//     distance to that box is at least R_l (with a relative margin of 1e-4) is dropped by a
+//     stable in-tile compaction, so the pair loop runs over the controls that can reach the
+//     workgroup only. Dropped pairs have phi = 0 exactly, the order of the kept ones is
+//     unchanged, and each level's sum runs over all its tiles before psi is applied once, so the
+//     sums equal the uncut ones bit for bit whatever the tiling;
 //   * the wall-distance reduction keeps only points with d < max_l D_l: the prefix of a resident
 //     volume stored in spatially compact blocks ordered by their smallest wall distance, or a
 //     stable two-kernel compaction that also writes +0.0 to every dropped point;
