@@ -219,3 +219,13 @@ def test_greedy_long_level_with_several_tiles_per_workgroup(gctx, orc, monkeypat
                                   cap=w.cap_total(), seeds=w.seeds)
     torch.cuda.synchronize()
     _check_same(orc, w, _LONG_LEVEL["ref"], cs)
+
+
+@pytest.mark.parametrize("mode", ["lean", "cg", "kernels"])
+def test_greedy_every_schedule_matches_oracle(gctx, orc, monkeypatch, mode):
+    """The three schedules of an iteration (persistent kernel with one barrier, cooperative-groups
+    grid barriers, two launches) select the oracle's control points."""
+    monkeypatch.setenv("RBF_GREEDY_MODE", mode)
+    w = synth.workload_cfg0()
+    ref, cs = _greedy_both(gctx, orc, w)
+    _check_same(orc, w, ref, cs)
