@@ -157,8 +157,10 @@ rbf_status rbf_greedy_select(rbf_ctx ctx, const rbf_greedy_params *params, int64
 
 /* Weights of the interpolant through n_c given points, eq. (9): Phi_cc alpha = dsc with
  * Phi_cc[i][j] = phi(||x_i - x_j|| / radius). FP64 blocked Cholesky (trailing updates on FP64
- * matrix cores) and triangular solves. xc, dsc, alpha: device [dim][n_c]. Blocking.
- * RBF_E_NOT_SPD when a pivot is not positive (repeated or numerically coincident points). */
+ * matrix cores) and triangular solves. xc, dsc, alpha: device [dim][n_c], n_c in 1..65536.
+ * Blocking. RBF_E_NOT_SPD when a pivot is not positive (repeated or numerically coincident
+ * points). Each substitution is one launch whose workgroups wait for earlier blocks with a
+ * bounded poll; a wait that gives up (never in a healthy run) returns RBF_E_DEVICE. */
 rbf_status rbf_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c,
                              const double *xc, const double *dsc, double *alpha, int32_t basis,
                              void *stream);

@@ -5,11 +5,17 @@
 //                             L_ik = A_ik L_kk^-T           (panel: one wave per row block,
 //                                                            a row per lane, L_kk in LDS)
 //                             A_ij -= L_ik L_jk^T, i >= j > k  (trailing update, FP64 MFMA)
-// then blocked forward and backward substitution for the dim right-hand sides. The trailing
-// update carries the n^3/3 flops and runs on v_mfma_f64_16x16x4_f64: each 256-lane workgroup
-// owns a 64x64 tile, each wave a 32x32 quarter as 2x2 MFMA blocks over the 64-deep product.
+// Blocks move between HBM and the waves' rows through LDS, so every global access is a
+// contiguous 512-byte row. The trailing update carries the n^3/3 flops and runs on
+// v_mfma_f64_16x16x4_f64: each 256-lane workgroup owns a 64x64 tile, each wave a 32x32 quarter as
+// 2x2 MFMA blocks over the 64-deep product.
+// The forward and backward substitutions for the dim right-hand sides are one launch each: the
+// workgroup owning a block row forms the inverse of its diagonal block while it waits, removes
+// the contributions of the finished blocks as each is published, and multiplies by the inverse,
+// so the chain from one block to the next is one flag, one 64x64 product and one 64x64 product.
 // A non-positive pivot raises a device flag reported as RBF_E_NOT_SPD.
 #include <cmath>
+#include <cstdlib>
 
 #include "basis.h"
 #include "internal.h"
@@ -30,6 +36,22 @@ __device__ __forceinline__ double sqrt_pos(double a)
     h = __builtin_fma(h, r, h);
     double d = __builtin_fma(-g, g, a);
     return __builtin_fma(d, h, g);
+}
+
+// sqrt(a) and 1/sqrt(a) to about an ulp: the v_rsq_f64 seed, one Goldschmidt step, a correction
+// of the root and a last step on the reciprocal.
+__device__ __forceinline__ void sqrt_and_rsqrt(double a, double &sq, double &inv)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y;
+    double h = 0.5 * y;
+    double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    const double d = __builtin_fma(-g, g, a);
+    sq = __builtin_fma(d, h, g);
+    r = __builtin_fma(-sq, h, 0.5);
+    inv = 2.0 * __builtin_fma(h, r, h);
 }
 
 // Phi[i][j] = phi(||x_i - x_j|| / R) for the lower triangle (upper left untouched), padded
@@ -65,18 +87,38 @@ __device__ __forceinline__ double lane_value(double v, int l)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Factor the diagonal block: one wave, lane i holds row i in registers. At step j the pivot is
-// read from lane j, column j is scaled in every lane and written once to LDS, and each lane
-// subtracts L[i][j] L[c][j] from its entries c > j with L[c][j] read as an LDS broadcast.
-// Entries above the diagonal are left out of every read that matters and are not stored.
-__global__ __launch_bounds__(NB) void c_diag(double *A, int64_t lda, int64_t k0, int32_t *bad)
+// Load / store a 64x64 block of the row-major matrix through LDS: lane t moves column t of every
+// row, so each access is one contiguous row.
+__device__ __forceinline__ void block_to_lds(const double *A, int64_t lda, int64_t r0, int64_t c0,
+                                             double (*T)[NB + 1])
 {
-    __shared__ __align__(16) double col[NB];
+    const int t = threadIdx.x;
+#pragma unroll 8
+    for (int r = 0; r < NB; ++r) T[r][t] = A[(r0 + r) * lda + c0 + t];
+}
+
+// LDS hand-off between the lanes of one wave (the only wave taking part).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Factor the diagonal block k0 in place, by one wave (lane i = threadIdx.x < 64) holding row i in
+// registers. At step j the pivot is read from lane j, column j is scaled in every lane (by the
+// reciprocal root, so the serial chain holds no division) and written once to LDS, and each lane
+// subtracts L[i][j] L[c][j] from its entries c > j with L[c][j] read as an LDS broadcast. Entries
+// above the diagonal are never read and are not stored. T and col are LDS scratch.
+__device__ __forceinline__ void diag_factor(double *A, int64_t lda, int64_t k0, int32_t *bad,
+                                            double (*T)[NB + 1], double *col)
+{
     const int i = threadIdx.x;
-    double *ar = A + (k0 + i) * lda + k0;
+    block_to_lds(A, lda, k0, k0, T);
+    wave_lds_sync();
     double r[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) r[c] = c <= i ? ar[c] : 0.0;
+    for (int c = 0; c < NB; ++c) r[c] = c <= i ? T[i][c] : 0.0;
     bool sing = false;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -86,14 +128,13 @@ __global__ __launch_bounds__(NB) void c_diag(double *A, int64_t lda, int64_t k0,
             sing = true;
             d = 1.0;
         }
-        const double sd = sqrt(d);
-        const double lij = i > j ? r[j] / sd : 0.0;
+        double sd, inv;
+        sqrt_and_rsqrt(d, sd, inv);
+        const double lij = i > j ? r[j] * inv : 0.0;
         r[j] = i > j ? lij : (i == j ? sd : 0.0);
         if (j + 1 < NB) {
             col[i] = lij;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            wave_lds_sync();
 #pragma unroll
             for (int c = j + 1; c < NB; ++c) r[c] = __builtin_fma(-lij, col[c], r[c]);
             __builtin_amdgcn_wave_barrier();
@@ -101,8 +142,19 @@ __global__ __launch_bounds__(NB) void c_diag(double *A, int64_t lda, int64_t k0,
     }
     if (sing && i == 0) *bad = 1;
 #pragma unroll
-    for (int c = 0; c < NB; ++c)
-        if (c <= i) ar[c] = r[c];
+    for (int c = 0; c < NB; ++c) T[i][c] = r[c];
+    wave_lds_sync();
+#pragma unroll 8
+    for (int rr = 0; rr < NB; ++rr)
+        if (i <= rr) A[(k0 + rr) * lda + k0 + i] = T[rr][i];
+}
+
+// The first diagonal block (every later one is factored by the trailing update that finishes it).
+__global__ __launch_bounds__(NB) void c_diag(double *A, int64_t lda, int64_t k0, int32_t *bad)
+{
+    __shared__ double T[NB][NB + 1];
+    __shared__ __align__(16) double col[NB];
+    diag_factor(A, lda, k0, bad, T, col);
 }
 
 // acc(64x64, this wave's 32x32 quarter) = Ablk(64x64) * Bblk(64x64)^T from LDS via FP64 MFMA.
@@ -133,35 +185,48 @@ __device__ __forceinline__ void tile_abt(const double (*Ab)[NB + 1], const doubl
 }
 
 // Panel: L_ik = A_ik L_kk^-T for every row block i below k. One wave per row block, lane r holds
-// row r of A_ik and solves x L_kk^T = a by columns (x_m = a_m / L_mm, then a_j -= x_m L_jm for
-// j > m), with L_kk in LDS read as broadcasts.
+// row r of A_ik and solves x L_kk^T = a by columns (x_m = a_m / L_mm, as a product with the
+// reciprocal formed beforehand, then a_j -= x_m L_jm for j > m), with L_kk in LDS read as
+// broadcasts.
 __global__ __launch_bounds__(NB) void c_panel(double *A, int64_t lda, int64_t k0)
 {
     __shared__ double L[NB][NB + 1];
+    __shared__ double T[NB][NB + 1];
+    __shared__ double rinv[NB];
     const int t = threadIdx.x;
-    for (int r = 0; r < NB; ++r) L[r][t] = t <= r ? A[(k0 + r) * lda + k0 + t] : 0.0;
     const int64_t i0 = k0 + NB * (1 + (int64_t)blockIdx.x);
-    double *ar = A + (i0 + t) * lda + k0;
+    block_to_lds(A, lda, k0, k0, L);
+    block_to_lds(A, lda, i0, k0, T);
+    __syncthreads();
+    rinv[t] = 1.0 / L[t][t];
     double a[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) a[c] = ar[c];
+    for (int c = 0; c < NB; ++c) a[c] = T[t][c];
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
-        const double x = a[m] / L[m][m];
+        const double x = a[m] * rinv[m];
         a[m] = x;
 #pragma unroll
         for (int j = m + 1; j < NB; ++j) a[j] = __builtin_fma(-x, L[j][m], a[j]);
     }
 #pragma unroll
-    for (int c = 0; c < NB; ++c) ar[c] = a[c];
+    for (int c = 0; c < NB; ++c) T[t][c] = a[c];
+    __syncthreads();
+#pragma unroll 8
+    for (int r = 0; r < NB; ++r) A[(i0 + r) * lda + k0 + t] = T[r][t];
 }
 
-// Trailing update A_ij -= L_ik L_jk^T over the lower block triangle j <= i below block k.
-__global__ __launch_bounds__(256) void c_trailing(double *A, int64_t lda, int64_t k0, int64_t nbr)
+// Trailing update A_ij -= L_ik L_jk^T over the lower block triangle j <= i below block k. Tile 0
+// is the next diagonal block; once its update is stored it is final, so wave 0 of that workgroup
+// factors it while the other tiles are still being updated (the diagonal step leaves the critical
+// path wherever the trailing update is longer).
+__global__ __launch_bounds__(256) void c_trailing(double *A, int64_t lda, int64_t k0, int64_t nbr,
+                                                  int32_t *bad)
 {
     __shared__ double ab[NB][NB + 1];
     __shared__ double bb[NB][NB + 1];
+    __shared__ __align__(16) double col[NB];
     // linear block index -> (bi, bj) with 0 <= bj <= bi < nbr (blocks after k)
     int64_t t = blockIdx.x;
     int64_t bi = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -185,105 +250,200 @@ __global__ __launch_bounds__(256) void c_trailing(double *A, int64_t lda, int64_
         for (int c = 0; c < 2; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int row = r0 + r * 16 + (lane >> 4) + 4 * v, col = c0 + c * 16 + (lane & 15);
-                A[(i0 + row) * lda + j0 + col] -= acc[r][c][v];
+                int row = r0 + r * 16 + (lane >> 4) + 4 * v, cc = c0 + c * 16 + (lane & 15);
+                A[(i0 + row) * lda + j0 + cc] -= acc[r][c][v];
             }
-}
-
-// Forward substitution L y = b for rows [b0, b0 + 64), then b_i -= L_i,blk y_blk below.
-template <int DIM>
-__global__ __launch_bounds__(256) void c_fwd(const double *A, int64_t lda, double *b, int64_t ldb,
-                                             int64_t n, int64_t b0, double *yout)
-{
-    __shared__ double Lb[NB][NB + 1];
-    __shared__ double yb[DIM][NB];
-    __shared__ double rinv[NB];                         // 1 / L[i][i], off the serial chain
-    const int nb = (int)min<int64_t>(NB, n - b0);
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-        int r = e / NB, c = e % NB;
-        Lb[r][c] = (r < nb && c <= r) ? A[(b0 + r) * lda + b0 + c] : (r == c ? 1.0 : 0.0);
-    }
-    if (threadIdx.x < NB)
-        for (int k = 0; k < DIM; ++k) yb[k][threadIdx.x] = threadIdx.x < nb ? b[k * ldb + b0 + threadIdx.x] : 0.0;
-    __syncthreads();
-    if (threadIdx.x < NB) rinv[threadIdx.x] = 1.0 / Lb[threadIdx.x][threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x < NB) {
-        const int j = threadIdx.x;
-        double rhs[DIM];
-        for (int k = 0; k < DIM; ++k) rhs[k] = yb[k][j];
-        for (int i = 0; i < nb; ++i) {
-            // x_i from lane i's finished right-hand side, the same value in every lane
-            const double ri = rinv[i];
-            double xi[DIM];
-            for (int k = 0; k < DIM; ++k) xi[k] = lane_value(rhs[k], i) * ri;
-            if (j > i)
-                for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[j][i], xi[k], rhs[k]);
-            if (j == i)
-                for (int k = 0; k < DIM; ++k) rhs[k] = xi[k];
-        }
-        for (int k = 0; k < DIM; ++k) yb[k][j] = rhs[k];
-    }
-    __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x < nb)
-        for (int k = 0; k < DIM; ++k) yout[k * ldb + b0 + threadIdx.x] = yb[k][threadIdx.x];
-    for (int64_t r = b0 + nb + (int64_t)blockIdx.x * 256 + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * 256) {
-        double acc[DIM];
-        for (int k = 0; k < DIM; ++k) acc[k] = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            double l = A[r * lda + b0 + i];
-            for (int k = 0; k < DIM; ++k) acc[k] = __builtin_fma(l, yb[k][i], acc[k]);
-        }
-        for (int k = 0; k < DIM; ++k) b[k * ldb + r] -= acc[k];
+    if (t == 0) {
+        __syncthreads();   // the tile's stores by all four waves, before wave 0 reads it back
+        if (threadIdx.x < NB) diag_factor(A, lda, k0 + NB, bad, ab, col);
     }
 }
 
-// Backward substitution L^T x = y for rows [b0, b1), then y_j -= L_blk,j x_blk above.
-template <int DIM>
-__global__ __launch_bounds__(256) void c_bwd(const double *A, int64_t lda, double *y, int64_t ldy,
-                                             int64_t b0, int64_t b1, double *xout)
+// ---- substitutions, one launch each -------------------------------------------------------------
+// Chain state (int32, zeroed before the factorization): [0] forward ticket, [1] backward ticket,
+// [2] fault (a wait gave up), [3] non-positive pivot, then one done flag per block for the forward
+// pass and one per block for the backward pass.
+constexpr int CH_HDR = 16;
+// Default bound on the polls of one wait (each after a short sleep, seconds in all): far beyond any
+// chain, it only ends a wait that could never be met, with the fault flag instead of a hang.
+// RBF_SOLVE_SPIN_LIMIT overrides it.
+constexpr unsigned long long SOLVE_SPIN_LIMIT = 1ull << 22;
+
+struct ChainArgs {
+    const double *A;
+    int64_t lda, n, nblk;
+    double *y;        // [dim][n]: forward result
+    double *dinv;     // [nblk][64][64]: inverses of the diagonal blocks, row-major
+    int32_t *st;
+    unsigned long long spin_limit;
+    int32_t want;     // value of a published done flag
+};
+
+// Workgroup-uniform wait until *flag reaches a.want; false when the wait gave up (fault raised).
+__device__ __forceinline__ bool wait_published(const ChainArgs &a, const int32_t *flag, int32_t &ok_sh)
 {
-    __shared__ double Lb[NB][NB + 1];
-    __shared__ double xb[DIM][NB];
-    __shared__ double rinv[NB];                         // 1 / L[i][i], off the serial chain
-    const int nb = (int)(b1 - b0);
-    for (int e = threadIdx.x; e < NB * NB; e += 256) {
-        int r = e / NB, c = e % NB;
-        Lb[r][c] = (r < nb && c <= r) ? A[(b0 + r) * lda + b0 + c] : (r == c ? 1.0 : 0.0);
-    }
-    if (threadIdx.x < NB)
-        for (int k = 0; k < DIM; ++k) xb[k][threadIdx.x] = threadIdx.x < nb ? y[k * ldy + b0 + threadIdx.x] : 0.0;
     __syncthreads();
-    if (threadIdx.x < NB) rinv[threadIdx.x] = 1.0 / Lb[threadIdx.x][threadIdx.x];
-    __syncthreads();
-    if (threadIdx.x < NB) {
-        const int j = threadIdx.x;
-        double rhs[DIM];
-        for (int k = 0; k < DIM; ++k) rhs[k] = xb[k][j];
-        for (int i = nb - 1; i >= 0; --i) {
-            const double ri = rinv[i];
-            double xi[DIM];
-            for (int k = 0; k < DIM; ++k) xi[k] = lane_value(rhs[k], i) * ri;
-            if (j < i)
-                for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[i][j], xi[k], rhs[k]);
-            if (j == i)
-                for (int k = 0; k < DIM; ++k) rhs[k] = xi[k];
+    if (threadIdx.x == 0) {
+        unsigned long long spins = 0;
+        int32_t ok = 1;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.want) {
+            if (spins++ >= a.spin_limit ||
+                ((spins & 63) == 0 && __hip_atomic_load(&a.st[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
         }
-        for (int k = 0; k < DIM; ++k) xb[k][j] = rhs[k];
+        if (!ok) __hip_atomic_store(&a.st[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        ok_sh = ok;
     }
     __syncthreads();
-    if (blockIdx.x == 0 && threadIdx.x < nb)
-        for (int k = 0; k < DIM; ++k) xout[k * ldy + b0 + threadIdx.x] = xb[k][threadIdx.x];
-    for (int64_t jj = (int64_t)blockIdx.x * 256 + threadIdx.x; jj < b0; jj += (int64_t)gridDim.x * 256) {
-        double acc[DIM];
-        for (int k = 0; k < DIM; ++k) acc[k] = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            double l = A[(b0 + i) * lda + jj];
-            for (int k = 0; k < DIM; ++k) acc[k] = __builtin_fma(l, xb[k][i], acc[k]);
-        }
-        for (int k = 0; k < DIM; ++k) y[k * ldy + jj] -= acc[k];
+    return ok_sh != 0;
+}
+
+__device__ __forceinline__ void publish(const ChainArgs &a, int32_t *flag)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Dv = inv(L) for the lower-triangular L in LDS (rows and columns past the matrix are identity):
+// lane t forms column t by forward substitution in the same order as the panel solve (x_j =
+// r_j / L_jj with the reciprocal formed beforehand, then r_i -= L_ij x_j for i > j), the column
+// of L read as broadcasts.
+__device__ __forceinline__ void tri_inverse(const double (*L)[NB + 1], double (*Dv)[NB + 1], double *rl)
+{
+    const int t = threadIdx.x;
+    rl[t] = 1.0 / L[t][t];
+    __syncthreads();
+    double r[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) r[i] = i == t ? 1.0 : 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const double xj = r[j] * rl[j];
+        r[j] = xj;
+#pragma unroll
+        for (int i = j + 1; i < NB; ++i) r[i] = __builtin_fma(-L[i][j], xj, r[i]);
     }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) Dv[j][t] = r[j];
+}
+
+// Forward substitution L y = b. The workgroup with ticket kb owns rows [64 kb, 64 kb + 64): lane t
+// keeps row t of b minus the finished blocks' contributions L_kb,j y_j, then y_kb = inv(L_kb,kb)
+// times that. Tickets follow the order in which workgroups start, so a workgroup only waits for
+// blocks owned by workgroups already running.
+template <int DIM>
+__global__ __launch_bounds__(NB) void c_fwd_chain(ChainArgs a, const double *b)
+{
+    __shared__ double Ls[NB][NB + 1];
+    __shared__ double Dv[NB][NB + 1];
+    __shared__ double vec[DIM][NB];
+    __shared__ double rl[NB];
+    __shared__ int32_t sh_kb, ok_sh;
+    const int t = threadIdx.x;
+    if (t == 0) sh_kb = __hip_atomic_fetch_add(&a.st[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t kb = sh_kb, k0 = kb * NB;
+    block_to_lds(a.A, a.lda, k0, k0, Ls);
+    __syncthreads();
+    tri_inverse(Ls, Dv, rl);
+    double *dk = a.dinv + kb * NB * NB;   // for the backward pass, stored off the chain
+#pragma unroll 8
+    for (int r = 0; r < NB; ++r) dk[r * NB + threadIdx.x] = Dv[r][threadIdx.x];
+    double acc[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) acc[k] = k0 + t < a.n ? b[k * a.n + k0 + t] : 0.0;
+    for (int64_t j = 0; j < kb; ++j) {
+        __syncthreads();
+        block_to_lds(a.A, a.lda, k0, j * NB, Ls);
+        if (!wait_published(a, &a.st[CH_HDR + j], ok_sh)) return;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) vec[k][t] = a.y[k * a.n + j * NB + t];   // j < kb: a whole block
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int c = 0; c < NB; c += 2) {
+                s0 = __builtin_fma(Ls[t][c], vec[k][c], s0);
+                s1 = __builtin_fma(Ls[t][c + 1], vec[k][c + 1], s1);
+            }
+            acc[k] -= s0 + s1;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) vec[k][t] = acc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NB; c += 2) {
+            s0 = __builtin_fma(Dv[t][c], vec[k][c], s0);
+            s1 = __builtin_fma(Dv[t][c + 1], vec[k][c + 1], s1);
+        }
+        if (k0 + t < a.n) a.y[k * a.n + k0 + t] = s0 + s1;
+    }
+    publish(a, &a.st[CH_HDR + kb]);
+}
+
+// Backward substitution L^T x = y, blocks from the last: the workgroup owning block kb keeps, in
+// lane t, entry t of y_kb minus sum over finished j > kb of (L_j,kb^T x_j), then x_kb =
+// inv(L_kb,kb)^T times that, with the inverse the forward pass stored.
+template <int DIM>
+__global__ __launch_bounds__(NB) void c_bwd_chain(ChainArgs a, double *x)
+{
+    __shared__ double Ls[NB][NB + 1];
+    __shared__ double Dv[NB][NB + 1];
+    __shared__ double vec[DIM][NB];
+    __shared__ int32_t sh_kb, ok_sh;
+    const int t = threadIdx.x;
+    if (t == 0) sh_kb = __hip_atomic_fetch_add(&a.st[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t kb = a.nblk - 1 - sh_kb, k0 = kb * NB;
+    const double *dk = a.dinv + kb * NB * NB;
+#pragma unroll 8
+    for (int r = 0; r < NB; ++r) Dv[r][t] = dk[r * NB + t];
+    double acc[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) acc[k] = k0 + t < a.n ? a.y[k * a.n + k0 + t] : 0.0;
+    for (int64_t j = a.nblk - 1; j > kb; --j) {
+        __syncthreads();
+        block_to_lds(a.A, a.lda, j * NB, k0, Ls);
+        if (!wait_published(a, &a.st[CH_HDR + a.nblk + j], ok_sh)) return;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) vec[k][t] = j * NB + t < a.n ? x[k * a.n + j * NB + t] : 0.0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int r = 0; r < NB; r += 2) {
+                s0 = __builtin_fma(Ls[r][t], vec[k][r], s0);
+                s1 = __builtin_fma(Ls[r + 1][t], vec[k][r + 1], s1);
+            }
+            acc[k] -= s0 + s1;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) vec[k][t] = acc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < NB; r += 2) {
+            s0 = __builtin_fma(Dv[r][t], vec[k][r], s0);
+            s1 = __builtin_fma(Dv[r + 1][t], vec[k][r + 1], s1);
+        }
+        if (k0 + t < a.n) x[k * a.n + k0 + t] = s0 + s1;
+    }
+    publish(a, &a.st[CH_HDR + a.nblk + kb]);
 }
 
 template <int DIM>
@@ -293,43 +453,51 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
     Pool *pool = ctx->pool.get();
     const int64_t lda = ((n + NB - 1) / NB) * NB;
     const int64_t nblk = lda / NB;
-    DevBuf bA, bFlag, bW, bY;
+    const size_t st_bytes = sizeof(int32_t) * (size_t)(CH_HDR + 2 * nblk);
+    DevBuf bA, bSt, bDinv, bY;
     RBF_TRY(bA.get(pool, sizeof(double) * (size_t)lda * (size_t)lda));
-    RBF_TRY(bFlag.get(pool, sizeof(int32_t)));
-    RBF_TRY(bW.get(pool, sizeof(double) * DIM * (size_t)n));
+    RBF_TRY(bSt.get(pool, st_bytes));
+    RBF_TRY(bDinv.get(pool, sizeof(double) * (size_t)nblk * NB * NB));
     RBF_TRY(bY.get(pool, sizeof(double) * DIM * (size_t)n));
     double *A = bA.as<double>();
-    RBF_HIP(hipMemsetAsync(bFlag.ptr, 0, sizeof(int32_t), s));
+    int32_t *st = bSt.as<int32_t>();
+    RBF_HIP(hipMemsetAsync(st, 0, st_bytes, s));
     hipLaunchKernelGGL(c_build<DIM>, dim3((unsigned)std::min<int64_t>(lda, 8192)), dim3(256), 0, s,
                        xc, n, lda, 1.0 / radius, basis, A);
     for (int64_t kb = 0; kb < nblk; ++kb) {
         const int64_t k0 = kb * NB, rest = nblk - kb - 1;
-        hipLaunchKernelGGL(c_diag, dim3(1), dim3(NB), 0, s, A, lda, k0, bFlag.as<int32_t>());
+        if (kb == 0) hipLaunchKernelGGL(c_diag, dim3(1), dim3(NB), 0, s, A, lda, k0, st + 3);
         if (rest > 0) {
             hipLaunchKernelGGL(c_panel, dim3((unsigned)rest), dim3(NB), 0, s, A, lda, k0);
             hipLaunchKernelGGL(c_trailing, dim3((unsigned)(rest * (rest + 1) / 2)), dim3(256), 0, s, A, lda,
-                               k0, rest);
+                               k0, rest, st + 3);
         }
     }
     RBF_HIP(hipGetLastError());
-    // W = dsc (updated below each block), Y = L^-1 dsc, alpha = L^-T Y (Y updated above).
-    RBF_HIP(hipMemcpyAsync(bW.ptr, dsc, sizeof(double) * DIM * n, hipMemcpyDeviceToDevice, s));
-    for (int64_t b0 = 0; b0 < n; b0 += NB) {
-        unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n - b0 + 255) / 256, 1024));
-        hipLaunchKernelGGL(c_fwd<DIM>, dim3(gb), dim3(256), 0, s, A, lda, bW.as<double>(), n, n, b0,
-                           bY.as<double>());
-    }
-    for (int64_t b1 = n; b1 > 0; b1 -= NB) {
-        int64_t b0 = std::max<int64_t>(0, b1 - NB);
-        unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b0 + 255) / 256, 1024));
-        hipLaunchKernelGGL(c_bwd<DIM>, dim3(gb), dim3(256), 0, s, A, lda, bY.as<double>(), n, b0, b1,
-                           alpha);
-    }
+    ChainArgs ca{};
+    ca.A = A;
+    ca.lda = lda;
+    ca.n = n;
+    ca.nblk = nblk;
+    ca.y = bY.as<double>();
+    ca.dinv = bDinv.as<double>();
+    ca.st = st;
+    ca.spin_limit = SOLVE_SPIN_LIMIT;
+    if (const char *e = getenv("RBF_SOLVE_SPIN_LIMIT")) ca.spin_limit = strtoull(e, nullptr, 10);
+    // RBF_SOLVE_UNMET_WAITS=1 makes every wait ask for a flag value no block publishes, so each
+    // gives up at the spin limit: the failure path, reached with every kernel still exiting.
+    ca.want = 1;
+    if (const char *e = getenv("RBF_SOLVE_UNMET_WAITS")) ca.want = atoi(e) ? 2 : 1;
+    hipLaunchKernelGGL(c_fwd_chain<DIM>, dim3((unsigned)nblk), dim3(NB), 0, s, ca, dsc);
+    hipLaunchKernelGGL(c_bwd_chain<DIM>, dim3((unsigned)nblk), dim3(NB), 0, s, ca, alpha);
     RBF_HIP(hipGetLastError());
-    int32_t bad = 0;
-    RBF_HIP(hipMemcpyAsync(&bad, bFlag.ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t flags[4] = {0, 0, 0, 0};
+    RBF_HIP(hipMemcpyAsync(flags, st, sizeof(flags), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
-    if (bad) return fail(RBF_E_NOT_SPD, "Phi_cc is not numerically positive definite (n=%lld)", (long long)n);
+    if (flags[3]) return fail(RBF_E_NOT_SPD, "Phi_cc is not numerically positive definite (n=%lld)", (long long)n);
+    if (flags[2])
+        return fail(RBF_E_DEVICE, "weight solve: a substitution wait gave up after %llu polls (n=%lld)",
+                    ca.spin_limit, (long long)n);
     return RBF_OK;
 }
 

@@ -150,6 +150,46 @@ def test_weight_solve_matches_oracle(gctx, orc):
         assert np.abs(back - dsc).max() <= 1e-11
 
 
+@pytest.mark.parametrize("n", [1, 64, 65, 127, 128, 129, 2048])
+def test_weight_solve_block_edges(gctx, orc, n):
+    """Block-size edges of the 64-row factorization and the one-launch substitutions: a single
+    point, whole blocks, one row into a new block, and 32 blocks chained in one launch."""
+    rng = np.random.default_rng(1000 + n)
+    dim = 3 if n % 2 else 2
+    xc = rng.uniform(-1, 1, (dim, n))
+    dsc = rng.uniform(-0.05, 0.05, (dim, n))
+    R = 0.35 if n > 500 else 0.8
+    print(f"case solve edges dim={dim} n={n} R={R}", flush=True)
+    st, ref = orc.solve_weights(R, xc, dsc)
+    assert st == 0
+    a = rbfdef.rbf_solve_weights(gctx, R, to_dev(xc), to_dev(dsc))
+    torch.cuda.synchronize()
+    a = a.cpu().numpy()
+    assert normwise(a, ref) <= 1e-7
+    back = orc.evaluate(R, xc, a, xc)
+    assert np.abs(back - dsc).max() <= 1e-11
+
+
+def test_weight_solve_unmet_wait_is_a_device_error(gctx, orc, monkeypatch):
+    """Waits that can never be met (forced from the host: no block publishes the flag value they
+    ask for) give up at the spin limit and report RBF_E_DEVICE; the context still solves after."""
+    rng = np.random.default_rng(77)
+    xc = rng.uniform(-1, 1, (2, 300))
+    dsc = rng.uniform(-0.05, 0.05, (2, 300))
+    monkeypatch.setenv("RBF_SOLVE_UNMET_WAITS", "1")
+    monkeypatch.setenv("RBF_SOLVE_SPIN_LIMIT", "2000")
+    print("case solve unmet waits n=300", flush=True)
+    with pytest.raises(rbfdef.RbfError) as e:
+        rbfdef.rbf_solve_weights(gctx, 0.8, to_dev(xc), to_dev(dsc))
+    assert e.value.status == rbfdef.RBF_E_DEVICE
+    monkeypatch.delenv("RBF_SOLVE_UNMET_WAITS")
+    monkeypatch.delenv("RBF_SOLVE_SPIN_LIMIT")
+    st, ref = orc.solve_weights(0.8, xc, dsc)
+    a = rbfdef.rbf_solve_weights(gctx, 0.8, to_dev(xc), to_dev(dsc))
+    torch.cuda.synchronize()
+    assert normwise(a.cpu().numpy(), ref) <= 1e-7
+
+
 def test_weight_solve_not_spd(gctx):
     xc = np.array([[0.0, 0.3, 0.3], [0.0, 0.1, 0.1]])
     with pytest.raises(rbfdef.RbfError) as e:
