@@ -1128,10 +1128,12 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         a.seeds = bSeeds.as<int64_t>() + seed_off[l];
         a.n_seeds = seed_off[l + 1] - seed_off[l];
         a.max_iter = a.n_seeds + a.cap_level + 2;
-        hipLaunchKernelGGL(g_init<DIM>, dim3((unsigned)g), dim3(64), 0, s, R, a.E, a.sel, n_s, a.part);
-        hipLaunchKernelGGL(g_begin, dim3(1), dim3(NT), 0, s, st, a.part, g, prm.eps_abs,
-                           prm.level_reduction, (int32_t)(l == prm.n_levels - 1));
-        RBF_HIP(hipGetLastError());
+        if (l == 0) {   // later levels start from the state the previous level's close prepared
+            hipLaunchKernelGGL(g_init<DIM>, dim3((unsigned)g), dim3(64), 0, s, R, a.E, a.sel, n_s, a.part);
+            hipLaunchKernelGGL(g_begin, dim3(1), dim3(NT), 0, s, st, a.part, g, prm.eps_abs,
+                               prm.level_reduction, (int32_t)(prm.n_levels == 1));
+            RBF_HIP(hipGetLastError());
+        }
         // Warm start from the resident basis of the same control points: copy V and L, then
         // y = L^-1 r_C and E = r - V y; the level continues from n0 columns.
         if (warm && l < (int)warm->size()) {
@@ -1297,10 +1299,11 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         total += n;
         out->level_off[l + 1] = (int32_t)total;
         used = l + 1;
-        // max ||dS_{l+1}|| decides whether another level is needed.
+        // max ||dS_{l+1}|| decides whether another level is needed; the same two launches set up
+        // level l + 1 (its residual, cleared selection flags and stop target).
         hipLaunchKernelGGL(g_init<DIM>, dim3((unsigned)g), dim3(64), 0, s, R, a.E, a.sel, n_s, a.part);
         hipLaunchKernelGGL(g_begin, dim3(1), dim3(NT), 0, s, st, a.part, g, prm.eps_abs,
-                           prm.level_reduction, 1);
+                           prm.level_reduction, (int32_t)(l + 2 >= prm.n_levels));
         RBF_HIP(hipGetLastError());
         RBF_HIP(hipMemcpyAsync(&hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
         RBF_HIP(hipStreamSynchronize(s));
