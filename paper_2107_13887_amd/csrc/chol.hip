@@ -302,7 +302,7 @@ __device__ __forceinline__ bool wait_published(const ChainArgs &a, const int32_t
     return ok_sh != 0;
 }
 
-__device__ __forceinline__ void publish(const ChainArgs &a, int32_t *flag)
+__device__ __forceinline__ void publish(int32_t *flag)
 {
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(NB) void c_fwd_chain(ChainArgs a, const double *b)
         }
         if (k0 + t < a.n) a.y[k * a.n + k0 + t] = s0 + s1;
     }
-    publish(a, &a.st[CH_HDR + kb]);
+    publish(&a.st[CH_HDR + kb]);
 }
 
 // Backward substitution L^T x = y, blocks from the last: the workgroup owning block kb keeps, in
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(NB) void c_bwd_chain(ChainArgs a, double *x)
         }
         if (k0 + t < a.n) x[k * a.n + k0 + t] = s0 + s1;
     }
-    publish(a, &a.st[CH_HDR + a.nblk + kb]);
+    publish(&a.st[CH_HDR + a.nblk + kb]);
 }
 
 template <int DIM>

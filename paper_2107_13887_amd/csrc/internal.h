@@ -117,6 +117,16 @@ struct Geometry {
     std::vector<std::vector<int64_t>> last_ctrl;
     std::vector<LevelCache> levels;   // resident Newton bases of the last finished request
     uint64_t cache_bytes = 0;         // device bytes held by `levels`
+    // Orders in which the resident kernel sums take their row groups (estimated heavy first, dealt
+    // across the compute units), one per launch shape, radii and support distances. Entries live
+    // as long as the geometry, since a launch on another stream may still read one.
+    struct GroupOrder {
+        int32_t P = 0, n_levels = 0;
+        double inv_r[RBF_MAX_LEVELS]{}, D[RBF_MAX_LEVELS]{};
+        DevBuf order;
+    };
+    std::mutex order_mu;
+    std::vector<GroupOrder> orders;
     double last_use = 0.0;
     int32_t refs = 0;        // queued or running requests (guarded by the server's lock)
     bool running = false;    // a request on this geometry is running
@@ -204,6 +214,7 @@ struct SumProblem {
     const int32_t *perm = nullptr;
     int64_t n_active = -1;
     const double *block_box = nullptr;   // [n_pad / BOXROWS][2 dim] box of every BOXROWS stored points
+    Geometry *geom = nullptr;            // resident geometry, whose cached row-group order the launch uses
 };
 
 // Enqueues the whole evaluation on `s`; scratch comes from the pool and is released
@@ -233,5 +244,10 @@ double now_seconds();
 
 // ---- serving (serve.cpp) --------------------------------------------------------------------------
 void server_shutdown(rbf_ctx ctx);   // stops the scheduler thread and drops its state
+// Row-group order of a resident kernel sum with P points per lane over n_groups groups of 256 P
+// stored rows: built on the first call for this shape, radii and support distances (one small
+// kernel and a host sort), then reused. *order is null when the cache is full.
+rbf_status resident_order(rbf_ctx ctx, Geometry &g, const SumProblem &pb, int P, int64_t n_groups,
+                          hipStream_t s, const int32_t **order);
 
 }  // namespace rbf

@@ -59,6 +59,7 @@ struct KArgs {
     unsigned long long *pairs;      // evaluated (point, control) pairs are added here, or null
     int64_t n_live;                 // rows from here on need no level (-1: every row may)
     const double *block_box;        // resident geometry: box of every BOXROWS stored rows [n / BOXROWS][2 DIM], or null
+    const int32_t *order;           // resident geometry: row group of workgroup x (a permutation), or null: group x
 };
 
 // A control is dropped for a workgroup when its squared distance to the workgroup's box, in units
@@ -254,7 +255,8 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
     __shared__ int seg[ML + 1];                         // level segments of the kept tile
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t n_work = a.n_work_dev ? *a.n_work_dev : a.n_work;
-    const int64_t wbase = (int64_t)blockIdx.x * (BLOCK * P);
+    const int64_t group = a.order ? (int64_t)a.order[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t wbase = group * (BLOCK * P);
     if (wbase >= n_work) return;
     const int split = blockIdx.y;
     // Rows from n_live on lie beyond every level's support (resident volume past its reduced
@@ -699,6 +701,12 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     S = std::min(S, env.max_split > 0 ? env.max_split : 64);
     if (env.split > 0) S = env.split;
     a.n_split = S;
+    // Resident geometry: workgroups take the row groups heaviest first, dealt across the compute
+    // units (RBF_KSUM_ORDER=0: stored order).
+    if (pb.geom) {
+        const char *e = getenv("RBF_KSUM_ORDER");
+        if (!(e && e[0] == '0')) RBF_TRY(resident_order(ctx, *pb.geom, pb, P, nbx, s, &a.order));
+    }
     if (S > 1) {
         RBF_TRY(partial.get(ctx->pool.get(), sizeof(double) * (size_t)S * DIM * n_rows));
         a.partial = partial.as<double>();

@@ -431,6 +431,72 @@ int64_t prefix_for(const Geometry &g, double D)
     return (int64_t)(it - g.block_dmin.begin()) * VBLOCK;
 }
 
+// Work estimate of each row group of a resident kernel sum (one workgroup per group of `rows`
+// stored rows): over the levels whose support distance reaches the group (its first row holds its
+// smallest wall distance, rows being sorted by it within each stored block), the surface points
+// within R_l of the group's box, from a sample of at most 4096 of them, each level weighted by
+// (1 / R_l)^(dim - 1), about how densely a level of radius R_l places its controls on the surface.
+struct OrderLevels {
+    int32_t n_levels;
+    double inv_r[RBF_MAX_LEVELS], D[RBF_MAX_LEVELS];
+};
+
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_group_weight(const double *xs, int64_t n_s, int64_t stride,
+                                                        const double *box, const double *d_sorted, int rows,
+                                                        OrderLevels lv, double *weight)
+{
+    __shared__ double red[4][RBF_MAX_LEVELS];
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    const double dmin = d_sorted[r0];
+    double lo[DIM], hi[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        lo[k] = HUGE_VAL;
+        hi[k] = -HUGE_VAL;
+    }
+    for (int b = 0; b < rows / BOXROWS; ++b) {
+        const double *bb = box + (r0 / BOXROWS + b) * 2 * DIM;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            lo[k] = fmin(lo[k], bb[k]);
+            hi[k] = fmax(hi[k], bb[DIM + k]);
+        }
+    }
+    double cnt[RBF_MAX_LEVELS];
+    for (int l = 0; l < RBF_MAX_LEVELS; ++l) cnt[l] = 0.0;
+    if (dmin < HUGE_VAL) {
+        for (int64_t j = (int64_t)threadIdx.x * stride; j < n_s; j += 256 * stride) {
+            double d2 = 0.0;
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                const double x = xs[k * n_s + j];
+                const double e = x < lo[k] ? lo[k] - x : (x > hi[k] ? x - hi[k] : 0.0);
+                d2 = __builtin_fma(e, e, d2);
+            }
+            for (int l = 0; l < lv.n_levels; ++l)
+                if (d2 * (lv.inv_r[l] * lv.inv_r[l]) < 1.00020001) cnt[l] += 1.0;
+        }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int l = 0; l < lv.n_levels; ++l) {
+        double c = cnt[l];
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+        if (lane == 0) red[w][l] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double wt = 0.0;
+        for (int l = 0; l < lv.n_levels; ++l) {
+            if (!(dmin < lv.D[l])) continue;
+            double f = 1.0;
+            for (int k = 1; k < DIM; ++k) f *= lv.inv_r[l];
+            wt += f * (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
+        }
+        weight[blockIdx.x] = wt;
+    }
+}
+
 uint64_t greedy_footprint(int dim, int64_t n_s, int64_t cap)
 {
     const uint64_t cols = (uint64_t)std::min<int64_t>(n_s, cap);
@@ -443,6 +509,75 @@ uint64_t greedy_footprint(int dim, int64_t n_s, int64_t cap)
 }
 
 }  // namespace
+
+rbf_status resident_order(rbf_ctx ctx, Geometry &g, const SumProblem &pb, int P, int64_t n_groups,
+                          hipStream_t s, const int32_t **order)
+{
+    *order = nullptr;
+    const int rows = 256 * P;
+    if (n_groups * rows != g.n_pad || pb.n_levels < 1 || pb.n_levels > RBF_MAX_LEVELS) return RBF_OK;
+    std::lock_guard<std::mutex> lk(g.order_mu);
+    for (const Geometry::GroupOrder &o : g.orders) {
+        bool same = o.P == P && o.n_levels == pb.n_levels;
+        for (int l = 0; same && l < pb.n_levels; ++l)
+            same = o.inv_r[l] == pb.lv[l].inv_r && o.D[l] == pb.lv[l].D;
+        if (same) {
+            *order = o.order.as<const int32_t>();
+            return RBF_OK;
+        }
+    }
+    if (g.orders.size() >= 16) return RBF_OK;   // many distinct requests: stored order
+    OrderLevels lv{};
+    lv.n_levels = pb.n_levels;
+    for (int l = 0; l < pb.n_levels; ++l) {
+        lv.inv_r[l] = pb.lv[l].inv_r;
+        lv.D[l] = pb.lv[l].D;
+    }
+    DevBuf bw;
+    RBF_TRY(bw.get(ctx->pool.get(), sizeof(double) * (size_t)n_groups));
+    const int64_t stride = std::max<int64_t>(1, (g.n_s + 4095) / 4096);
+    if (g.dim == 2)
+        hipLaunchKernelGGL(geo_group_weight<2>, dim3((unsigned)n_groups), dim3(256), 0, s, g.xs.as<const double>(), g.n_s,
+                           stride, g.block_box.as<const double>(), g.d_sorted.as<const double>(), rows, lv, bw.as<double>());
+    else
+        hipLaunchKernelGGL(geo_group_weight<3>, dim3((unsigned)n_groups), dim3(256), 0, s, g.xs.as<const double>(), g.n_s,
+                           stride, g.block_box.as<const double>(), g.d_sorted.as<const double>(), rows, lv, bw.as<double>());
+    RBF_HIP(hipGetLastError());
+    std::vector<double> wt((size_t)n_groups);
+    RBF_HIP(hipMemcpyAsync(wt.data(), bw.ptr, sizeof(double) * (size_t)n_groups, hipMemcpyDeviceToHost, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    // Heaviest first (stored order among equals), dealt to the compute units back and forth:
+    // workgroup x runs on unit x mod n_cu, every workgroup resident at once.
+    std::vector<int32_t> rank((size_t)n_groups);
+    for (int64_t i = 0; i < n_groups; ++i) rank[(size_t)i] = (int32_t)i;
+    std::stable_sort(rank.begin(), rank.end(), [&](int32_t x, int32_t y) { return wt[(size_t)x] > wt[(size_t)y]; });
+    const int64_t ncu = std::max(1, ctx->n_cu);
+    std::vector<int32_t> ord((size_t)n_groups, -1);
+    for (int64_t k = 0; k < n_groups; ++k) {
+        const int64_t r = k / ncu, c = k % ncu;
+        const bool whole = (r + 1) * ncu <= n_groups;   // the last, partial round is not reversed
+        const int64_t x = r * ncu + ((r & 1) && whole ? ncu - 1 - c : c);
+        ord[(size_t)x] = rank[(size_t)k];
+    }
+    std::vector<uint8_t> seen((size_t)n_groups, 0);
+    for (int32_t v : ord) {
+        if (v < 0 || v >= n_groups || seen[(size_t)v]) return fail(RBF_E_DEVICE, "row-group order is not a permutation");
+        seen[(size_t)v] = 1;
+    }
+    Geometry::GroupOrder o;
+    o.P = P;
+    o.n_levels = pb.n_levels;
+    for (int l = 0; l < pb.n_levels; ++l) {
+        o.inv_r[l] = pb.lv[l].inv_r;
+        o.D[l] = pb.lv[l].D;
+    }
+    RBF_TRY(o.order.get(ctx->pool.get(), sizeof(int32_t) * (size_t)n_groups));
+    RBF_HIP(hipMemcpyAsync(o.order.ptr, ord.data(), sizeof(int32_t) * (size_t)n_groups, hipMemcpyHostToDevice, s));
+    RBF_HIP(hipStreamSynchronize(s));
+    *order = o.order.as<const int32_t>();
+    g.orders.push_back(std::move(o));
+    return RBF_OK;
+}
 
 // ---- server ---------------------------------------------------------------------------------
 struct Req {
@@ -685,6 +820,7 @@ rbf_status Server::run(Req &q, hipStream_t s)
     pb.perm = g.perm.as<int32_t>();
     pb.n_active = prefix_for(g, dmax);
     pb.block_box = g.block_box.as<double>();
+    pb.geom = &g;
     pb.out = q.r.dv;
     pb.sign = -1.0;
     pb.precision = p.precision;
@@ -827,6 +963,7 @@ rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, 
     pb.perm = g->perm.as<int32_t>();
     pb.n_active = prefix_for(*g, dmax);
     pb.block_box = g->block_box.as<double>();
+    pb.geom = g;
     pb.out = dv;
     pb.sign = -1.0;
     pb.precision = precision;

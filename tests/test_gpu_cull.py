@@ -101,3 +101,33 @@ def test_culling_takes_effect(gctx, orc):
     err = np.sqrt(((dv.cpu().numpy() - ref) ** 2).sum(0)).max()
     assert err <= fp64_bound(scale, S)
     rbfdef.rbf_geom_release(gctx, geom)
+
+
+def test_row_group_order_changes_no_bits(gctx, orc, monkeypatch):
+    """Workgroups take the resident row groups heaviest first by an estimate, dealt back and forth
+    across the compute units (782 groups: three whole rounds and a partial one). The result is bit
+    for bit the one in stored order and the plain call's, also when the cached order is reused and
+    when other radii add a second order."""
+    w, res, xc = _case(orc, 512, 2, 500, 200000, [1.0, 0.2, 0.05])
+    D = [0.6, 0.6, 0.6]
+    print(f"case order n_v=200000 n_c={res.level_off[-1]}", flush=True)
+    geom = rbfdef.rbf_geom_create(gctx, to_dev(w.xs), to_dev(w.xv), to_dev(w.dwall))
+
+    def update(radius, setting):
+        monkeypatch.setenv("RBF_KSUM_ORDER", setting)
+        dv = torch.full((2, w.n_v), float("nan"), dtype=torch.float64, device="cuda:0")
+        rbfdef.rbf_geom_volume_update(gctx, geom, radius, D, list(res.level_off), to_dev(xc),
+                                      to_dev(res.alpha), dv)
+        torch.cuda.synchronize()
+        return dv
+
+    first, again, stored = update(w.radius, "1"), update(w.radius, "1"), update(w.radius, "0")
+    assert torch.equal(first, again) and torch.equal(first, stored)
+    assert not torch.isnan(first).any()
+    plain = rbfdef.rbf_volume_update(gctx, w.radius, D, list(res.level_off), to_dev(xc), to_dev(res.alpha),
+                                     to_dev(w.xv), to_dev(w.dwall))
+    torch.cuda.synchronize()
+    assert torch.equal(plain, first)
+    other = [1.1, 0.25, 0.06]
+    assert torch.equal(update(other, "1"), update(other, "0"))
+    rbfdef.rbf_geom_release(gctx, geom)
