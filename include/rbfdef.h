@@ -241,9 +241,9 @@ typedef struct {
  * D_l (no per-call compaction). Arguments as rbf_volume_update; dv is device [dim][n_v] in the
  * geometry's original point order, fully written (+0.0 where psi = 0). Enqueued on stream.
  * The first call on a geometry for a given set of radii and support distances also builds the
- * order in which the kernel's workgroups take the stored row groups (an estimate of their work,
- * heaviest first) and waits for the stream once to do so; later calls with the same set reuse it.
- * The order never changes a result. */
+ * order in which the kernel's workgroups take the stored row groups (heaviest first by the
+ * controls of that call each group keeps) and waits for the stream once to do so; later calls
+ * with the same set reuse it. The order never changes a result. */
 rbf_status rbf_geom_volume_update(rbf_ctx ctx, rbf_geom geom, int32_t n_levels, const double *radius,
                                   const double *D, const int32_t *level_off, int64_t ld_ctrl,
                                   const double *xc, const double *alpha, double *dv,

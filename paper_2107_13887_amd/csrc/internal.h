@@ -117,9 +117,10 @@ struct Geometry {
     std::vector<std::vector<int64_t>> last_ctrl;
     std::vector<LevelCache> levels;   // resident Newton bases of the last finished request
     uint64_t cache_bytes = 0;         // device bytes held by `levels`
-    // Orders in which the resident kernel sums take their row groups (estimated heavy first, dealt
-    // across the compute units), one per launch shape, radii and support distances. Entries live
-    // as long as the geometry, since a launch on another stream may still read one.
+    // Orders in which the resident kernel sums take their row groups (heaviest first by the controls
+    // each keeps, dealt across the compute units), one per launch shape, radii and support
+    // distances. Entries live as long as the geometry, since a launch on another stream may still
+    // read one.
     struct GroupOrder {
         int32_t P = 0, n_levels = 0;
         double inv_r[RBF_MAX_LEVELS]{}, D[RBF_MAX_LEVELS]{};
@@ -245,8 +246,10 @@ double now_seconds();
 // ---- serving (serve.cpp) --------------------------------------------------------------------------
 void server_shutdown(rbf_ctx ctx);   // stops the scheduler thread and drops its state
 // Row-group order of a resident kernel sum with P points per lane over n_groups groups of 256 P
-// stored rows: built on the first call for this shape, radii and support distances (one small
-// kernel and a host sort), then reused. *order is null when the cache is full.
+// stored rows: built on the first call for this shape, radii and support distances from that
+// call's controls (one small kernel and a host sort), then reused by later calls with the same
+// key whatever their controls (an order only decides which workgroup takes which group, never a
+// result). *order is null when the cache is full.
 rbf_status resident_order(rbf_ctx ctx, Geometry &g, const SumProblem &pb, int P, int64_t n_groups,
                           hipStream_t s, const int32_t **order);
 

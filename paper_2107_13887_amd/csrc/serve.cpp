@@ -431,22 +431,23 @@ int64_t prefix_for(const Geometry &g, double D)
     return (int64_t)(it - g.block_dmin.begin()) * VBLOCK;
 }
 
-// Work estimate of each row group of a resident kernel sum (one workgroup per group of `rows`
-// stored rows): over the levels whose support distance reaches the group (its first row holds its
-// smallest wall distance, rows being sorted by it within each stored block), the surface points
-// within R_l of the group's box, from a sample of at most 4096 of them, each level weighted by
-// (1 / R_l)^(dim - 1), about how densely a level of radius R_l places its controls on the surface.
+// Work of each row group of a resident kernel sum (one workgroup per group of `rows` stored
+// rows): the controls the workgroup will keep (those within R_l of the group's box, with the
+// kernel's margin), summed over the levels whose support distance reaches the group (its first row
+// holds its smallest wall distance, rows being sorted by it within each stored block). That is the
+// length of the workgroup's pair loop: its waves run side by side on the compute unit's SIMDs.
 struct OrderLevels {
     int32_t n_levels;
     double inv_r[RBF_MAX_LEVELS], D[RBF_MAX_LEVELS];
+    int64_t c_begin[RBF_MAX_LEVELS], c_end[RBF_MAX_LEVELS];
 };
 
 template <int DIM>
-__global__ __launch_bounds__(256) void geo_group_weight(const double *xs, int64_t n_s, int64_t stride,
-                                                        const double *box, const double *d_sorted, int rows,
-                                                        OrderLevels lv, double *weight)
+__global__ __launch_bounds__(256) void geo_group_weight(const double *xc, int64_t ld_ctrl, const double *box,
+                                                        const double *d_sorted, int rows, OrderLevels lv,
+                                                        double *weight)
 {
-    __shared__ double red[4][RBF_MAX_LEVELS];
+    __shared__ int32_t red[4][RBF_MAX_LEVELS];
     const int64_t r0 = (int64_t)blockIdx.x * rows;
     const double dmin = d_sorted[r0];
     double lo[DIM], hi[DIM];
@@ -463,36 +464,27 @@ __global__ __launch_bounds__(256) void geo_group_weight(const double *xs, int64_
             hi[k] = fmax(hi[k], bb[DIM + k]);
         }
     }
-    double cnt[RBF_MAX_LEVELS];
-    for (int l = 0; l < RBF_MAX_LEVELS; ++l) cnt[l] = 0.0;
-    if (dmin < HUGE_VAL) {
-        for (int64_t j = (int64_t)threadIdx.x * stride; j < n_s; j += 256 * stride) {
-            double d2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                const double x = xs[k * n_s + j];
-                const double e = x < lo[k] ? lo[k] - x : (x > hi[k] ? x - hi[k] : 0.0);
-                d2 = __builtin_fma(e, e, d2);
-            }
-            for (int l = 0; l < lv.n_levels; ++l)
-                if (d2 * (lv.inv_r[l] * lv.inv_r[l]) < 1.00020001) cnt[l] += 1.0;
-        }
-    }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int l = 0; l < lv.n_levels; ++l) {
-        double c = cnt[l];
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-        if (lane == 0) red[w][l] = c;
+        int32_t kept = 0;
+        if (dmin < lv.D[l])
+            for (int64_t c = lv.c_begin[l] + threadIdx.x; c < lv.c_end[l]; c += 256) {
+                double d2 = 0.0;
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) {
+                    const double x = xc[k * ld_ctrl + c];
+                    const double e = x < lo[k] ? lo[k] - x : (x > hi[k] ? x - hi[k] : 0.0);
+                    d2 = __builtin_fma(e, e, d2);
+                }
+                kept += d2 * (lv.inv_r[l] * lv.inv_r[l]) < 1.00020001 ? 1 : 0;
+            }
+        for (int off = 32; off > 0; off >>= 1) kept += __shfl_xor(kept, off, 64);
+        if (lane == 0) red[w][l] = kept;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         double wt = 0.0;
-        for (int l = 0; l < lv.n_levels; ++l) {
-            if (!(dmin < lv.D[l])) continue;
-            double f = 1.0;
-            for (int k = 1; k < DIM; ++k) f *= lv.inv_r[l];
-            wt += f * (red[0][l] + red[1][l] + red[2][l] + red[3][l]);
-        }
+        for (int l = 0; l < lv.n_levels; ++l) wt += (double)(red[0][l] + red[1][l] + red[2][l] + red[3][l]);
         weight[blockIdx.x] = wt;
     }
 }
@@ -532,16 +524,17 @@ rbf_status resident_order(rbf_ctx ctx, Geometry &g, const SumProblem &pb, int P,
     for (int l = 0; l < pb.n_levels; ++l) {
         lv.inv_r[l] = pb.lv[l].inv_r;
         lv.D[l] = pb.lv[l].D;
+        lv.c_begin[l] = pb.lv[l].c_begin;
+        lv.c_end[l] = pb.xc ? pb.lv[l].c_end : pb.lv[l].c_begin;
     }
     DevBuf bw;
     RBF_TRY(bw.get(ctx->pool.get(), sizeof(double) * (size_t)n_groups));
-    const int64_t stride = std::max<int64_t>(1, (g.n_s + 4095) / 4096);
     if (g.dim == 2)
-        hipLaunchKernelGGL(geo_group_weight<2>, dim3((unsigned)n_groups), dim3(256), 0, s, g.xs.as<const double>(), g.n_s,
-                           stride, g.block_box.as<const double>(), g.d_sorted.as<const double>(), rows, lv, bw.as<double>());
+        hipLaunchKernelGGL(geo_group_weight<2>, dim3((unsigned)n_groups), dim3(256), 0, s, pb.xc, pb.ld_ctrl,
+                           g.block_box.as<const double>(), g.d_sorted.as<const double>(), rows, lv, bw.as<double>());
     else
-        hipLaunchKernelGGL(geo_group_weight<3>, dim3((unsigned)n_groups), dim3(256), 0, s, g.xs.as<const double>(), g.n_s,
-                           stride, g.block_box.as<const double>(), g.d_sorted.as<const double>(), rows, lv, bw.as<double>());
+        hipLaunchKernelGGL(geo_group_weight<3>, dim3((unsigned)n_groups), dim3(256), 0, s, pb.xc, pb.ld_ctrl,
+                           g.block_box.as<const double>(), g.d_sorted.as<const double>(), rows, lv, bw.as<double>());
     RBF_HIP(hipGetLastError());
     std::vector<double> wt((size_t)n_groups);
     RBF_HIP(hipMemcpyAsync(wt.data(), bw.ptr, sizeof(double) * (size_t)n_groups, hipMemcpyDeviceToHost, s));

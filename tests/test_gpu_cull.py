@@ -104,10 +104,10 @@ def test_culling_takes_effect(gctx, orc):
 
 
 def test_row_group_order_changes_no_bits(gctx, orc, monkeypatch):
-    """Workgroups take the resident row groups heaviest first by an estimate, dealt back and forth
-    across the compute units (782 groups: three whole rounds and a partial one). The result is bit
-    for bit the one in stored order and the plain call's, also when the cached order is reused and
-    when other radii add a second order."""
+    """Workgroups take the resident row groups heaviest first (by the controls each keeps), dealt
+    back and forth across the compute units (782 groups: three whole rounds and a partial one). The
+    result is bit for bit the one in stored order and the plain call's, also when the cached order
+    is reused and when other radii add a second order."""
     w, res, xc = _case(orc, 512, 2, 500, 200000, [1.0, 0.2, 0.05])
     D = [0.6, 0.6, 0.6]
     print(f"case order n_v=200000 n_c={res.level_off[-1]}", flush=True)
