@@ -170,6 +170,29 @@ def test_weight_solve_block_edges(gctx, orc, n):
     assert np.abs(back - dsc).max() <= 1e-11
 
 
+def test_weight_solve_more_blocks_than_resident(gctx, orc):
+    """518 block rows: more substitution workgroups than the device holds at once (two per compute
+    unit, by LDS), so later ones start only as earlier ones finish, and the ticket order keeps every
+    wait on a block owned by a running workgroup. A jittered 182 x 182 grid with R three spacings
+    (well conditioned); checked by the interpolation residual at 300 sampled points (the oracle's
+    evaluation of the returned weights)."""
+    rng = np.random.default_rng(93)
+    m = 182
+    h = 2.0 / (m - 1)
+    gx, gy = np.meshgrid(np.linspace(-1, 1, m), np.linspace(-1, 1, m), indexing="ij")
+    xc = np.stack([gx.ravel(), gy.ravel()]) + rng.uniform(-0.2 * h, 0.2 * h, (2, m * m))
+    dsc = rng.uniform(-0.05, 0.05, (2, m * m))
+    R = 3.0 * h
+    print(f"case solve n={m * m} blocks={-(-m * m // 64)} R={R:.4f}", flush=True)
+    a = rbfdef.rbf_solve_weights(gctx, R, to_dev(xc), to_dev(dsc))
+    torch.cuda.synchronize()
+    idx = rng.choice(m * m, 300, replace=False)
+    back = orc.evaluate(R, xc, a.cpu().numpy(), np.ascontiguousarray(xc[:, idx]))
+    err = np.abs(back - dsc[:, idx]).max()
+    print(f"interpolation residual {err:.3e}")
+    assert err <= 1e-11
+
+
 def test_weight_solve_unmet_wait_is_a_device_error(gctx, orc, monkeypatch):
     """Waits that can never be met (forced from the host: no block publishes the flag value they
     ask for) give up at the spin limit and report RBF_E_DEVICE; the context still solves after."""
