@@ -19,6 +19,7 @@
 
 #include "basis.h"
 #include "internal.h"
+#include "trichain.h"
 
 namespace rbf {
 namespace {
@@ -264,10 +265,7 @@ __global__ __launch_bounds__(256) void c_trailing(double *A, int64_t lda, int64_
 // [2] fault (a wait gave up), [3] non-positive pivot, then one done flag per block for the forward
 // pass and one per block for the backward pass.
 constexpr int CH_HDR = 16;
-// Default bound on the polls of one wait (each after a short sleep, seconds in all): far beyond any
-// chain, it only ends a wait that could never be met, with the fault flag instead of a hang.
-// RBF_SOLVE_SPIN_LIMIT overrides it.
-constexpr unsigned long long SOLVE_SPIN_LIMIT = 1ull << 22;
+// RBF_SOLVE_SPIN_LIMIT overrides the bound on the polls of one wait.
 
 struct ChainArgs {
     const double *A;
@@ -278,58 +276,6 @@ struct ChainArgs {
     unsigned long long spin_limit;
     int32_t want;     // value of a published done flag
 };
-
-// Workgroup-uniform wait until *flag reaches a.want; false when the wait gave up (fault raised).
-__device__ __forceinline__ bool wait_published(const ChainArgs &a, const int32_t *flag, int32_t &ok_sh)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long spins = 0;
-        int32_t ok = 1;
-        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < a.want) {
-            if (spins++ >= a.spin_limit ||
-                ((spins & 63) == 0 && __hip_atomic_load(&a.st[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                ok = 0;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (!ok) __hip_atomic_store(&a.st[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        ok_sh = ok;
-    }
-    __syncthreads();
-    return ok_sh != 0;
-}
-
-__device__ __forceinline__ void publish(int32_t *flag)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Dv = inv(L) for the lower-triangular L in LDS (rows and columns past the matrix are identity):
-// lane t forms column t by forward substitution in the same order as the panel solve (x_j =
-// r_j / L_jj with the reciprocal formed beforehand, then r_i -= L_ij x_j for i > j), the column
-// of L read as broadcasts.
-__device__ __forceinline__ void tri_inverse(const double (*L)[NB + 1], double (*Dv)[NB + 1], double *rl)
-{
-    const int t = threadIdx.x;
-    rl[t] = 1.0 / L[t][t];
-    __syncthreads();
-    double r[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) r[i] = i == t ? 1.0 : 0.0;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const double xj = r[j] * rl[j];
-        r[j] = xj;
-#pragma unroll
-        for (int i = j + 1; i < NB; ++i) r[i] = __builtin_fma(-L[i][j], xj, r[i]);
-    }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) Dv[j][t] = r[j];
-}
 
 // Forward substitution L y = b. The workgroup with ticket kb owns rows [64 kb, 64 kb + 64): lane t
 // keeps row t of b minus the finished blocks' contributions L_kb,j y_j, then y_kb = inv(L_kb,kb)
@@ -349,7 +295,7 @@ __global__ __launch_bounds__(NB) void c_fwd_chain(ChainArgs a, const double *b)
     const int64_t kb = sh_kb, k0 = kb * NB;
     block_to_lds(a.A, a.lda, k0, k0, Ls);
     __syncthreads();
-    tri_inverse(Ls, Dv, rl);
+    tc_tri_inverse(Ls, Dv, rl);
     double *dk = a.dinv + kb * NB * NB;   // for the backward pass, stored off the chain
 #pragma unroll 8
     for (int r = 0; r < NB; ++r) dk[r * NB + threadIdx.x] = Dv[r][threadIdx.x];
@@ -359,7 +305,7 @@ __global__ __launch_bounds__(NB) void c_fwd_chain(ChainArgs a, const double *b)
     for (int64_t j = 0; j < kb; ++j) {
         __syncthreads();
         block_to_lds(a.A, a.lda, k0, j * NB, Ls);
-        if (!wait_published(a, &a.st[CH_HDR + j], ok_sh)) return;
+        if (!tc_wait(&a.st[CH_HDR + j], a.want, &a.st[2], a.spin_limit, ok_sh)) return;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) vec[k][t] = a.y[k * a.n + j * NB + t];   // j < kb: a whole block
         __syncthreads();
@@ -388,7 +334,7 @@ __global__ __launch_bounds__(NB) void c_fwd_chain(ChainArgs a, const double *b)
         }
         if (k0 + t < a.n) a.y[k * a.n + k0 + t] = s0 + s1;
     }
-    publish(&a.st[CH_HDR + kb]);
+    tc_publish(&a.st[CH_HDR + kb]);
 }
 
 // Backward substitution L^T x = y, blocks from the last: the workgroup owning block kb keeps, in
@@ -414,7 +360,7 @@ __global__ __launch_bounds__(NB) void c_bwd_chain(ChainArgs a, double *x)
     for (int64_t j = a.nblk - 1; j > kb; --j) {
         __syncthreads();
         block_to_lds(a.A, a.lda, j * NB, k0, Ls);
-        if (!wait_published(a, &a.st[CH_HDR + a.nblk + j], ok_sh)) return;
+        if (!tc_wait(&a.st[CH_HDR + a.nblk + j], a.want, &a.st[2], a.spin_limit, ok_sh)) return;
 #pragma unroll
         for (int k = 0; k < DIM; ++k) vec[k][t] = j * NB + t < a.n ? x[k * a.n + j * NB + t] : 0.0;
         __syncthreads();
@@ -443,7 +389,7 @@ __global__ __launch_bounds__(NB) void c_bwd_chain(ChainArgs a, double *x)
         }
         if (k0 + t < a.n) x[k * a.n + k0 + t] = s0 + s1;
     }
-    publish(&a.st[CH_HDR + a.nblk + kb]);
+    tc_publish(&a.st[CH_HDR + a.nblk + kb]);
 }
 
 template <int DIM>
@@ -482,7 +428,7 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
     ca.y = bY.as<double>();
     ca.dinv = bDinv.as<double>();
     ca.st = st;
-    ca.spin_limit = SOLVE_SPIN_LIMIT;
+    ca.spin_limit = TC_SPIN_LIMIT;
     if (const char *e = getenv("RBF_SOLVE_SPIN_LIMIT")) ca.spin_limit = strtoull(e, nullptr, 10);
     // RBF_SOLVE_UNMET_WAITS=1 makes every wait ask for a flag value no block publishes, so each
     // gives up at the spin limit: the failure path, reached with every kernel still exiting.

@@ -32,6 +32,7 @@
 
 #include "basis.h"
 #include "internal.h"
+#include "trichain.h"
 
 namespace cg = cooperative_groups;
 
@@ -735,67 +736,80 @@ __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
     }
 }
 
-// Blocked back substitution L^T alpha = y for the 64 rows [b0, b1) (all later rows done).
-// Every workgroup solves the diagonal block (cheap, redundant) and then removes the block's
-// contribution from its share of the rows above b0; workgroup 0 stores alpha.
+// Back substitution L^T alpha = y of a level's packed factor (row j at j (j + 1) / 2) in one
+// launch, 64-row blocks from the last, chained as in the dense solve: the workgroup owning a block
+// forms the inverse of its diagonal block, removes the contributions L_j,kb^T alpha_j of the later
+// blocks as each is published, multiplies by the inverse and publishes its block. It also gathers
+// its block's control coordinates. st: [0] ticket, then one done flag per block (zeroed before the
+// launch); a wait that gives up raises gs->fault.
 template <int DIM>
-__global__ __launch_bounds__(256) void g_backsolve(const double *Lpack, double *y, int64_t ld_y,
-                                                   double *alpha, int64_t ld_a, int64_t b0, int64_t b1)
+__global__ __launch_bounds__(64) void g_backsolve_chain(const double *Lpack, int64_t n, const double *y,
+                                                        int64_t ld_y, double *alpha, int64_t ld_a,
+                                                        const double *xs, int64_t n_s, const int64_t *ctrl,
+                                                        double *xc, int32_t *st, GState *gs,
+                                                        unsigned long long spin_limit)
 {
-    __shared__ double Lb[64][65];
-    __shared__ double inv[64];
-    __shared__ double xb[DIM][64];
-    const int nb = (int)(b1 - b0);
-    for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x) {
-        const int r = t / 64, c = t % 64;
-        Lb[r][c] = (r < nb && c <= r) ? Lpack[((b0 + r) * (b0 + r + 1)) / 2 + b0 + c] : 0.0;
-    }
-    if (threadIdx.x < 64) {
+    __shared__ double Ls[TC_NB][TC_NB + 1];
+    __shared__ double Dv[TC_NB][TC_NB + 1];
+    __shared__ double vec[DIM][TC_NB];
+    __shared__ double rl[TC_NB];
+    __shared__ int32_t sh_kb, ok_sh;
+    const int t = threadIdx.x;
+    const int64_t nblk = (n + TC_NB - 1) / TC_NB;
+    if (t == 0) sh_kb = __hip_atomic_fetch_add(&st[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t kb = nblk - 1 - sh_kb, k0 = kb * TC_NB;
+    if (k0 + t < n) {
+        const int64_t p = ctrl[k0 + t];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) xb[k][threadIdx.x] = threadIdx.x < nb ? y[k * ld_y + b0 + threadIdx.x] : 0.0;
+        for (int k = 0; k < DIM; ++k) xc[k * ld_a + k0 + t] = xs[k * n_s + p];
+    }
+    // Diagonal block, identity past the level's n rows.
+    for (int r = 0; r < TC_NB; ++r) {
+        const int64_t i = k0 + r;
+        Ls[r][t] = (i < n && t <= r) ? Lpack[(i * (i + 1)) / 2 + k0 + t] : (r == t ? 1.0 : 0.0);
     }
     __syncthreads();
-    if (threadIdx.x < 64) {
-        const int j = threadIdx.x;
-        inv[j] = j < nb ? 1.0 / Lb[j][j] : 0.0;
-        double rhs[DIM];
+    tc_tri_inverse(Ls, Dv, rl);
+    double acc[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) rhs[k] = xb[k][j];
-        for (int i = nb - 1; i >= 0; --i) {
-            const double ii = inv[i];
-            double xi[DIM];
+    for (int k = 0; k < DIM; ++k) acc[k] = k0 + t < n ? y[k * ld_y + k0 + t] : 0.0;
+    for (int64_t j = nblk - 1; j > kb; --j) {
+        __syncthreads();
+        for (int r = 0; r < TC_NB; ++r) {   // L_j,kb: columns k0 + t lie left of every row i >= 64 j
+            const int64_t i = j * TC_NB + r;
+            Ls[r][t] = i < n ? Lpack[(i * (i + 1)) / 2 + k0 + t] : 0.0;
+        }
+        if (!tc_wait(&st[1 + j], 1, &gs->fault, spin_limit, ok_sh)) return;
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) xi[k] = __shfl(rhs[k], i, 64) * ii;
-            if (j < i) {
+        for (int k = 0; k < DIM; ++k) vec[k][t] = j * TC_NB + t < n ? alpha[k * ld_a + j * TC_NB + t] : 0.0;
+        __syncthreads();
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) rhs[k] = __builtin_fma(-Lb[i][j], xi[k], rhs[k]);
-            } else if (j == i) {
+        for (int k = 0; k < DIM; ++k) {
+            double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) rhs[k] = xi[k];
+            for (int r = 0; r < TC_NB; r += 2) {
+                s0 = __builtin_fma(Ls[r][t], vec[k][r], s0);
+                s1 = __builtin_fma(Ls[r + 1][t], vec[k][r + 1], s1);
             }
-        }
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) xb[k][j] = rhs[k];
-        if (blockIdx.x == 0 && j < nb) {
-#pragma unroll
-            for (int k = 0; k < DIM; ++k) alpha[k * ld_a + b0 + j] = rhs[k];
+            acc[k] -= s0 + s1;
         }
     }
     __syncthreads();
-    // Rows above the block: y_j -= sum_{i in block} L[i][j] alpha_i.
-    for (int64_t jj = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; jj < b0;
-         jj += (int64_t)gridDim.x * blockDim.x) {
-        double acc[DIM];
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) acc[k] = 0.0;
-        for (int i = 0; i < nb; ++i) {
-            const double lij = Lpack[((b0 + i) * (b0 + i + 1)) / 2 + jj];
+    for (int k = 0; k < DIM; ++k) vec[k][t] = acc[k];
+    __syncthreads();
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) acc[k] = __builtin_fma(lij, xb[k][i], acc[k]);
+    for (int k = 0; k < DIM; ++k) {
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < TC_NB; r += 2) {
+            s0 = __builtin_fma(Dv[r][t], vec[k][r], s0);
+            s1 = __builtin_fma(Dv[r + 1][t], vec[k][r + 1], s1);
         }
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) y[k * ld_y + jj] -= acc[k];
+        if (k0 + t < n) alpha[k * ld_a + k0 + t] = s0 + s1;
     }
+    tc_publish(&st[1 + kb]);
 }
 
 // ---- warm start from a resident basis --------------------------------------------------------
@@ -961,18 +975,6 @@ __global__ __launch_bounds__(256) void g_maxdiff(const double *r, const double *
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-template <int DIM>
-__global__ __launch_bounds__(256) void g_gather(const double *xs, int64_t n_s, const int64_t *ctrl,
-                                                int64_t n, double *xc, int64_t ld)
-{
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n;
-         j += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = ctrl[j];
-#pragma unroll
-        for (int k = 0; k < DIM; ++k) xc[k * ld + j] = xs[k * n_s + p];
-    }
-}
-
 __global__ void g_finite(const double *a, int64_t n, int32_t *bad)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -1064,6 +1066,11 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         RBF_HIP(hipMemcpyAsync(bSeeds.ptr, seeds_h.data(), sizeof(int64_t) * seeds_h.size(),
                                hipMemcpyHostToDevice, s));
     RBF_HIP(hipMemsetAsync(st, 0, sizeof(GState), s));
+    // Ticket and done flags of every level's chained back substitution, zeroed once.
+    const int64_t chain_stride = 1 + (cols + TC_NB - 1) / TC_NB;
+    DevBuf bChain;
+    RBF_TRY(bChain.get(pool, sizeof(int32_t) * (size_t)(prm.n_levels * chain_stride)));
+    RBF_HIP(hipMemsetAsync(bChain.ptr, 0, sizeof(int32_t) * (size_t)(prm.n_levels * chain_stride), s));
     RBF_HIP(hipMemcpyAsync(R, ds, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
 
     // Execution mode: "lean" (one barrier per iteration), "cg" (cooperative-groups grid
@@ -1223,17 +1230,12 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         // Weights: L^T alpha = y, blocked from the bottom.
         double *alpha = out->alpha + total;
         if (n > 0) {
-            RBF_HIP(hipMemcpy2DAsync(R2, sizeof(double) * cols, a.coef, sizeof(double) * cols,
-                                     sizeof(double) * n, DIM, hipMemcpyDeviceToDevice, s));
-            for (int64_t b1 = n; b1 > 0; b1 -= 64) {
-                const int64_t b0 = std::max<int64_t>(0, b1 - 64);
-                const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((b0 + 255) / 256, 1024));
-                hipLaunchKernelGGL(g_backsolve<DIM>, dim3(gb), dim3(256), 0, s, a.Lpack, R2, cols, alpha,
-                                   out->capacity, b0, b1);
-            }
-            const unsigned gg = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 1024));
-            hipLaunchKernelGGL(g_gather<DIM>, dim3(gg), dim3(256), 0, s, xs, n_s, a.ctrl, n,
-                               out->xc + total, out->capacity);
+            // One launch: the chained block back substitution, which also gathers the controls.
+            const int64_t nblk = (n + TC_NB - 1) / TC_NB;
+            hipLaunchKernelGGL(g_backsolve_chain<DIM>, dim3((unsigned)nblk), dim3(TC_NB), 0, s, a.Lpack, n,
+                               (const double *)a.coef, cols, alpha, out->capacity, xs, n_s,
+                               (const int64_t *)a.ctrl, out->xc + total,
+                               bChain.as<int32_t>() + (size_t)l * (size_t)chain_stride, st, a.spin_limit);
             RBF_HIP(hipGetLastError());
             // dS_{l+1} = dS_l - Phi_sC alpha at every surface point, FP64 kernel sum.
             SumProblem pb;
@@ -1307,6 +1309,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         RBF_HIP(hipGetLastError());
         RBF_HIP(hipMemcpyAsync(&hs, st, sizeof(GState), hipMemcpyDeviceToHost, s));
         RBF_HIP(hipStreamSynchronize(s));
+        if (hs.fault)
+            return fail(RBF_E_DEVICE, "greedy level %d: a wait of the back substitution gave up", l);
         out->level_max_err[l] = std::sqrt(hs.rmax2);
         out->level_seconds[l] = now_seconds() - t_level;
         if (std::sqrt(hs.rmax2) < prm.eps_abs || out->level_stop[l] == RBF_STOP_CAP) break;
