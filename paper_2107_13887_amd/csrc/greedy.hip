@@ -738,10 +738,12 @@ __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
 
 // Back substitution L^T alpha = y of a level's packed factor (row j at j (j + 1) / 2) in one
 // launch, 64-row blocks from the last, chained as in the dense solve: the workgroup owning a block
-// forms the inverse of its diagonal block, removes the contributions L_j,kb^T alpha_j of the later
-// blocks as each is published, multiplies by the inverse and publishes its block. It also gathers
-// its block's control coordinates. st: [0] ticket, then one done flag per block (zeroed before the
-// launch); a wait that gives up raises gs->fault.
+// removes the contributions L_j,kb^T alpha_j of the later blocks as each is published, then solves
+// its diagonal block by substitution (lane i holds row i; the reciprocals of the pivots are formed
+// beforehand and each finished unknown is broadcast from its lane) and publishes the block. It
+// also gathers its block's control coordinates. A level has few blocks, so the substitution stays
+// on the chain rather than an inverse formed while waiting. st: [0] ticket, then one done flag
+// per block (zeroed before the launch); a wait that gives up raises gs->fault.
 template <int DIM>
 __global__ __launch_bounds__(64) void g_backsolve_chain(const double *Lpack, int64_t n, const double *y,
                                                         int64_t ld_y, double *alpha, int64_t ld_a,
@@ -749,8 +751,8 @@ __global__ __launch_bounds__(64) void g_backsolve_chain(const double *Lpack, int
                                                         double *xc, int32_t *st, GState *gs,
                                                         unsigned long long spin_limit)
 {
-    __shared__ double Ls[TC_NB][TC_NB + 1];
-    __shared__ double Dv[TC_NB][TC_NB + 1];
+    __shared__ double Ld[TC_NB][TC_NB + 1];   // the diagonal block
+    __shared__ double Ls[TC_NB][TC_NB + 1];   // one later block's rows, L_j,kb
     __shared__ double vec[DIM][TC_NB];
     __shared__ double rl[TC_NB];
     __shared__ int32_t sh_kb, ok_sh;
@@ -764,21 +766,28 @@ __global__ __launch_bounds__(64) void g_backsolve_chain(const double *Lpack, int
 #pragma unroll
         for (int k = 0; k < DIM; ++k) xc[k * ld_a + k0 + t] = xs[k * n_s + p];
     }
-    // Diagonal block, identity past the level's n rows.
+    // Diagonal block, identity past the level's n rows. Every lane loads from a valid element (row
+    // and column clamped into the packed triangle) and selects afterwards, so the loads carry no
+    // branch and 16 of them are in flight.
+#pragma unroll 16
     for (int r = 0; r < TC_NB; ++r) {
-        const int64_t i = k0 + r;
-        Ls[r][t] = (i < n && t <= r) ? Lpack[(i * (i + 1)) / 2 + k0 + t] : (r == t ? 1.0 : 0.0);
+        const int64_t i = min(k0 + r, n - 1);
+        const int64_t c = min(k0 + (int64_t)t, i);
+        const double v = Lpack[(i * (i + 1)) / 2 + c];
+        Ld[r][t] = (k0 + r < n && t <= r) ? v : (r == t ? 1.0 : 0.0);
     }
     __syncthreads();
-    tc_tri_inverse(Ls, Dv, rl);
-    double acc[DIM];
+    rl[t] = 1.0 / Ld[t][t];
+    double x[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) acc[k] = k0 + t < n ? y[k * ld_y + k0 + t] : 0.0;
+    for (int k = 0; k < DIM; ++k) x[k] = k0 + t < n ? y[k * ld_y + k0 + t] : 0.0;
     for (int64_t j = nblk - 1; j > kb; --j) {
         __syncthreads();
+#pragma unroll 16
         for (int r = 0; r < TC_NB; ++r) {   // L_j,kb: columns k0 + t lie left of every row i >= 64 j
-            const int64_t i = j * TC_NB + r;
-            Ls[r][t] = i < n ? Lpack[(i * (i + 1)) / 2 + k0 + t] : 0.0;
+            const int64_t i = min(j * TC_NB + r, n - 1);   // a row of block j (64 j < n)
+            const double v = Lpack[(i * (i + 1)) / 2 + k0 + t];
+            Ls[r][t] = j * TC_NB + r < n ? v : 0.0;
         }
         if (!tc_wait(&st[1 + j], 1, &gs->fault, spin_limit, ok_sh)) return;
 #pragma unroll
@@ -792,22 +801,26 @@ __global__ __launch_bounds__(64) void g_backsolve_chain(const double *Lpack, int
                 s0 = __builtin_fma(Ls[r][t], vec[k][r], s0);
                 s1 = __builtin_fma(Ls[r + 1][t], vec[k][r + 1], s1);
             }
-            acc[k] -= s0 + s1;
+            x[k] -= s0 + s1;
         }
     }
     __syncthreads();
+    for (int i = TC_NB - 1; i >= 0; --i) {
+        const double ri = rl[i];
+        double xi[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) vec[k][t] = acc[k];
-    __syncthreads();
+        for (int k = 0; k < DIM; ++k) xi[k] = __shfl(x[k], i, 64) * ri;
+        if (t < i) {
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) {
-        double s0 = 0.0, s1 = 0.0;
+            for (int k = 0; k < DIM; ++k) x[k] = __builtin_fma(-Ld[i][t], xi[k], x[k]);
+        } else if (t == i) {
 #pragma unroll
-        for (int r = 0; r < TC_NB; r += 2) {
-            s0 = __builtin_fma(Dv[r][t], vec[k][r], s0);
-            s1 = __builtin_fma(Dv[r + 1][t], vec[k][r + 1], s1);
+            for (int k = 0; k < DIM; ++k) x[k] = xi[k];
         }
-        if (k0 + t < n) alpha[k * ld_a + k0 + t] = s0 + s1;
+    }
+    if (k0 + t < n) {
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) alpha[k * ld_a + k0 + t] = x[k];
     }
     tc_publish(&st[1 + kb]);
 }
