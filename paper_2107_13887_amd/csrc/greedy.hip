@@ -837,9 +837,18 @@ __global__ __launch_bounds__(256) void g_fwdsolve(const double *Lpack, double *b
     __shared__ double inv[64];
     __shared__ double xb[DIM][64];
     const int nb = (int)(b1 - b0);
-    for (int t = threadIdx.x; t < 64 * 64; t += blockDim.x) {
+    // Every thread loads a valid element (row and column clamped into the block's triangle) and
+    // masks it afterwards: no branch around the loads, all 16 in flight. Masked entries (above the
+    // diagonal or past the block's rows) may become -0 and are never read for a result.
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {   // launched with 256 threads: 16 passes cover the 64 x 64 block
+        const int t = (int)threadIdx.x + 256 * q;
         const int r = t / 64, c = t % 64;
-        Lb[r][c] = (r < nb && c <= r) ? Lpack[((b0 + r) * (b0 + r + 1)) / 2 + b0 + c] : 0.0;
+        const int64_t i = b0 + min(r, nb - 1);
+        const int64_t cc = b0 + min(c, (int)(i - b0));
+        const double v = Lpack[(i * (i + 1)) / 2 + cc];
+        Lb[r][c] = v * ((r < nb && c <= r) ? 1.0 : 0.0);   // a mask, not a select the compiler could
+                                                            // turn back into a branch around the load
     }
     if (threadIdx.x < 64) {
 #pragma unroll
