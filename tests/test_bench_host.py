@@ -1,0 +1,59 @@
+"""Host-side logic of bench.py (no GPU): the roofline's slot model, the match between the committed
+HBM counter summaries and the kernel source they were taken on, and the one-GPU guard."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_min_slots_model():
+    # C2: dim subtractions + dim FMAs for r^2 + 4 for the quarter-rate root + 1 - eta, max, t^2,
+    # t^4, 4 eta + 1, product (6) + dim accumulating FMAs.
+    assert bench.min_slots(2, "c2", "fp64") == 2 + 2 + 4 + 6 + 2 + 1
+    assert bench.min_slots(3, "c2", "fp64") == 3 + 3 + 4 + 6 + 3 + 1
+    assert bench.min_slots(2, "c2", "mixed") == bench.min_slots(2, "c2", "fp64") + 1
+    order = [bench.min_slots(3, b, "fp64") for b in ("c0", "c2", "c4", "c6")]
+    assert order == sorted(order)
+    # The peak in pairs/s is the lane-slot rate over the slots per pair.
+    assert bench.VALU_LANE_OPS == pytest.approx(256 * 64 * 2.4e9)
+    assert bench.VALU_LANE_OPS / bench.min_slots(2, "c2", "fp64") / 1e9 == pytest.approx(2313.035, rel=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_committed_traffic_matches_current_kernel(precision):
+    """The default workload's counter summaries were taken on the kernel source as it stands, so
+    the bench reports their traffic; it lies a little above the algorithmic bytes of the launch."""
+    path = os.path.join(ROOT, "profiles", f"traffic_volume_ksum_cfg1_{precision}.txt")
+    text = open(path).read()
+    assert f"ksum_source_sha256_16: {bench.kernel_source_hash()}" in text
+    t = bench.measured_traffic("cfg1", precision)
+    assert t is not None and 10e6 < t < 30e6
+
+
+def test_traffic_dropped_for_another_kernel_source(tmp_path, monkeypatch):
+    """A change to the code of the kernel-sum source (not to its comments) drops the traffic."""
+    csrc = tmp_path / "paper_2107_13887_amd" / "csrc"
+    csrc.mkdir(parents=True)
+    shutil.copytree(os.path.join(ROOT, "profiles"), tmp_path / "profiles")
+    src = open(os.path.join(ROOT, "paper_2107_13887_amd", "csrc", "ksum.hip")).read()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+
+    (csrc / "ksum.hip").write_text("// another comment\n/* and a block\n comment */\n" + src + "\n\n")
+    assert bench.measured_traffic("cfg1", "fp64") is not None
+
+    (csrc / "ksum.hip").write_text(src.replace("__launch_bounds__(BLOCK)", "__launch_bounds__(BLOCK, 2)", 1))
+    assert bench.measured_traffic("cfg1", "fp64") is None
+    assert bench.measured_traffic("no_such_workload", "fp64") is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
