@@ -25,15 +25,18 @@ def test_min_slots_model():
     assert bench.VALU_LANE_OPS / bench.min_slots(2, "c2", "fp64") / 1e9 == pytest.approx(2313.035, rel=1e-6)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_committed_traffic_matches_current_kernel(precision):
-    """The default workload's counter summaries were taken on the kernel source as it stands, so
-    the bench reports their traffic; it lies a little above the algorithmic bytes of the launch."""
-    path = os.path.join(ROOT, "profiles", f"traffic_volume_ksum_cfg1_{precision}.txt")
+@pytest.mark.parametrize("workload,precision", [("cfg1", "fp64"), ("cfg1", "mixed"), ("cfg2", "fp64")])
+def test_committed_traffic_matches_current_kernel(workload, precision):
+    """The committed counter summaries were taken on the kernel source as it stands, so the bench
+    reports their traffic, which lies within a factor 1.5 of the launch's algorithmic bytes
+    (prefix rows x (dim + 1) x 8 + 4 read, all stored rows x dim x 8 written, the rest 4 B read)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_volume_ksum_{workload}_{precision}.txt")
     text = open(path).read()
     assert f"ksum_source_sha256_16: {bench.kernel_source_hash()}" in text
-    t = bench.measured_traffic("cfg1", precision)
-    assert t is not None and 10e6 < t < 30e6
+    dim, n_red, n_rows = {"cfg1": (2, 243304, 400384), "cfg2": (3, 2832398, 4000256)}[workload]
+    algo = n_red * ((dim + 1) * 8 + 4) + (n_rows - n_red) * 4 + n_rows * dim * 8
+    t = bench.measured_traffic(workload, precision)
+    assert t is not None and algo / 1.5 < t < algo * 1.5
 
 
 def test_traffic_dropped_for_another_kernel_source(tmp_path, monkeypatch):
