@@ -9,6 +9,14 @@
 
 namespace rbf {
 
+// hipcc gives every translation unit with kernels a constructor that registers its GPU code
+// object and hands the matching unregistration to atexit(); exit() runs such handlers in reverse
+// order of registration. Initialising the HIP runtime first (priority 101 sorts this constructor
+// ahead of those at the default priority) makes every exit handler the runtime, or a profiler
+// attached to it, registers while it initialises older than the unregistrations, so those run
+// first, against a runtime that is still whole. Without a device the call just fails.
+__attribute__((constructor(101))) static void init_runtime_before_modules() { (void)hipInit(0); }
+
 static thread_local char g_err[512] = "";
 
 void set_error(const char *fmt, ...)

@@ -401,10 +401,10 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
     const int64_t nblk = lda / NB;
     const size_t st_bytes = sizeof(int32_t) * (size_t)(CH_HDR + 2 * nblk);
     DevBuf bA, bSt, bDinv, bY;
-    RBF_TRY(bA.get(pool, sizeof(double) * (size_t)lda * (size_t)lda));
-    RBF_TRY(bSt.get(pool, st_bytes));
-    RBF_TRY(bDinv.get(pool, sizeof(double) * (size_t)nblk * NB * NB));
-    RBF_TRY(bY.get(pool, sizeof(double) * DIM * (size_t)n));
+    RBF_TRY(bA.get(pool, sizeof(double) * (size_t)lda * (size_t)lda, s));
+    RBF_TRY(bSt.get(pool, st_bytes, s));
+    RBF_TRY(bDinv.get(pool, sizeof(double) * (size_t)nblk * NB * NB, s));
+    RBF_TRY(bY.get(pool, sizeof(double) * DIM * (size_t)n, s));
     double *A = bA.as<double>();
     int32_t *st = bSt.as<int32_t>();
     RBF_HIP(hipMemsetAsync(st, 0, st_bytes, s));
@@ -440,6 +440,7 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
     int32_t flags[4] = {0, 0, 0, 0};
     RBF_HIP(hipMemcpyAsync(flags, st, sizeof(flags), hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
+    settle_all(bA, bSt, bDinv, bY);
     if (flags[3]) return fail(RBF_E_NOT_SPD, "Phi_cc is not numerically positive definite (n=%lld)", (long long)n);
     if (flags[2])
         return fail(RBF_E_DEVICE, "weight solve: a substitution wait gave up after %llu polls (n=%lld)",

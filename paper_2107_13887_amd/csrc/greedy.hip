@@ -1049,19 +1049,19 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     // 512 bytes: workgroups that read the same column of their tiles at the same moment then fall
     // on different memory channels instead of one.
     const int64_t ldt = cols | 1;
-    RBF_TRY(bV.get(pool, sizeof(double) * (size_t)ldt * (size_t)((n_s + UPB - 1) / UPB) * UPB));
-    RBF_TRY(bL.get(pool, sizeof(double) * (size_t)(cols * (cols + 1) / 2 + 1)));
-    RBF_TRY(bE.get(pool, sizeof(double) * DIM * (size_t)n_s));
-    RBF_TRY(bR.get(pool, sizeof(double) * DIM * (size_t)n_s));
-    RBF_TRY(bR2.get(pool, sizeof(double) * DIM * (size_t)n_s));
-    RBF_TRY(bSel.get(pool, (size_t)n_s));
-    RBF_TRY(bPart.get(pool, sizeof(Cand) * (size_t)g));
-    RBF_TRY(bState.get(pool, sizeof(GState)));
-    RBF_TRY(bCoef.get(pool, sizeof(double) * DIM * (size_t)cols));
-    RBF_TRY(bHist.get(pool, sizeof(double) * (size_t)cap));
-    RBF_TRY(bFlag.get(pool, sizeof(int32_t)));
+    RBF_TRY(bV.get(pool, sizeof(double) * (size_t)ldt * (size_t)((n_s + UPB - 1) / UPB) * UPB, s));
+    RBF_TRY(bL.get(pool, sizeof(double) * (size_t)(cols * (cols + 1) / 2 + 1), s));
+    RBF_TRY(bE.get(pool, sizeof(double) * DIM * (size_t)n_s, s));
+    RBF_TRY(bR.get(pool, sizeof(double) * DIM * (size_t)n_s, s));
+    RBF_TRY(bR2.get(pool, sizeof(double) * DIM * (size_t)n_s, s));
+    RBF_TRY(bSel.get(pool, (size_t)n_s, s));
+    RBF_TRY(bPart.get(pool, sizeof(Cand) * (size_t)g, s));
+    RBF_TRY(bState.get(pool, sizeof(GState), s));
+    RBF_TRY(bCoef.get(pool, sizeof(double) * DIM * (size_t)cols, s));
+    RBF_TRY(bHist.get(pool, sizeof(double) * (size_t)cap, s));
+    RBF_TRY(bFlag.get(pool, sizeof(int32_t), s));
     const int32_t n_seed_total = prm.seed_off ? prm.seed_off[prm.n_levels] : 1;
-    RBF_TRY(bSeeds.get(pool, sizeof(int64_t) * (size_t)std::max(1, n_seed_total)));
+    RBF_TRY(bSeeds.get(pool, sizeof(int64_t) * (size_t)std::max(1, n_seed_total), s));
     double *R = bR.as<double>(), *R2 = bR2.as<double>();
     GState *st = bState.as<GState>();
 
@@ -1091,7 +1091,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     // Ticket and done flags of every level's chained back substitution, zeroed once.
     const int64_t chain_stride = 1 + (cols + TC_NB - 1) / TC_NB;
     DevBuf bChain;
-    RBF_TRY(bChain.get(pool, sizeof(int32_t) * (size_t)(prm.n_levels * chain_stride)));
+    RBF_TRY(bChain.get(pool, sizeof(int32_t) * (size_t)(prm.n_levels * chain_stride), s));
     RBF_HIP(hipMemsetAsync(bChain.ptr, 0, sizeof(int32_t) * (size_t)(prm.n_levels * chain_stride), s));
     RBF_HIP(hipMemcpyAsync(R, ds, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
 
@@ -1111,10 +1111,10 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
                        : cooperative_blocks(mode == 0 ? (const void *)g_level_lean<DIM> : (const void *)g_level<DIM>,
                                             ctx->n_cu);
     DevBuf bBar, bE2, bPart2;
-    RBF_TRY(bBar.get(pool, sizeof(GridBar)));
+    RBF_TRY(bBar.get(pool, sizeof(GridBar), s));
     if (mode == 0 && coop_max > 0) {
-        RBF_TRY(bE2.get(pool, sizeof(double) * DIM * (size_t)n_s));
-        RBF_TRY(bPart2.get(pool, sizeof(Cand) * (size_t)g));
+        RBF_TRY(bE2.get(pool, sizeof(double) * DIM * (size_t)n_s, s));
+        RBF_TRY(bPart2.get(pool, sizeof(Cand) * (size_t)g, s));
     }
     GArgs a{};
     a.st = st;
@@ -1280,8 +1280,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
                 // measured error that decides whether its volume sums may run in FP32.
                 const int64_t nb = (n_s + 255) / 256;
                 DevBuf bT, bPart;
-                RBF_TRY(bT.get(pool, sizeof(double) * DIM * n_s));
-                RBF_TRY(bPart.get(pool, sizeof(double) * nb));
+                RBF_TRY(bT.get(pool, sizeof(double) * DIM * n_s, s));
+                RBF_TRY(bPart.get(pool, sizeof(double) * nb, s));
                 SumProblem pf = pb;
                 pf.lv[0].fp32 = 1;
                 pf.base = nullptr;
@@ -1294,6 +1294,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
                 std::vector<double> ph(nb);
                 RBF_HIP(hipMemcpyAsync(ph.data(), bPart.ptr, sizeof(double) * nb, hipMemcpyDeviceToHost, s));
                 RBF_HIP(hipStreamSynchronize(s));
+                settle_all(bT, bPart);
                 out->level_fp32_err[l] = std::sqrt(*std::max_element(ph.begin(), ph.end()));
             }
             std::swap(R, R2);
@@ -1349,6 +1350,7 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         RBF_HIP(hipMemcpyAsync(out->err_hist, bHist.ptr, sizeof(double) * (size_t)std::min<int64_t>(hs.n_iter, cap),
                                hipMemcpyDeviceToDevice, s));
     RBF_HIP(hipStreamSynchronize(s));
+    settle_all(bV, bL, bE, bR, bR2, bSel, bPart, bState, bCoef, bHist, bFlag, bSeeds, bChain, bBar, bE2, bPart2);
     bool cap_hit = false, brk = false;
     for (int l = 0; l < used; ++l) {
         cap_hit |= out->level_stop[l] == RBF_STOP_CAP;

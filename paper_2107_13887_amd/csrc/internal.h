@@ -67,27 +67,52 @@ class Pool {
     std::deque<Deferred> deferred_;
 };
 
-// RAII device buffer from the pool. release_after() hands it back stream-ordered.
+// RAII device buffer from the pool. A buffer obtained with get(pool, bytes, s) is bound to the
+// stream s that its work is enqueued on: its destructor (an early return after some launches
+// included) hands it back stream-ordered, so no other caller can receive it while kernels already
+// enqueued on s may still use it. release_after() hands it back stream-ordered at once.
 struct DevBuf {
     Pool *pool = nullptr;
     void *ptr = nullptr;
+    hipStream_t stream = nullptr;
+    bool bound = false;
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : pool(o.pool), ptr(o.ptr) { o.ptr = nullptr; }
-    ~DevBuf() { if (ptr && pool) pool->free_now(ptr); }
-    rbf_status get(Pool *pl, size_t bytes) {
-        if (ptr && pool) pool->free_now(ptr);
-        pool = pl;
+    DevBuf(DevBuf &&o) noexcept : pool(o.pool), ptr(o.ptr), stream(o.stream), bound(o.bound) { o.ptr = nullptr; }
+    ~DevBuf() { drop(); }
+    void drop()
+    {
+        if (ptr && pool) {
+            if (bound) (void)pool->free_after(ptr, stream);
+            else pool->free_now(ptr);
+        }
         ptr = nullptr;
+    }
+    rbf_status get(Pool *pl, size_t bytes)
+    {
+        drop();
+        pool = pl;
+        bound = false;
+        return pl->alloc(&ptr, bytes);
+    }
+    rbf_status get(Pool *pl, size_t bytes, hipStream_t s)
+    {
+        drop();
+        pool = pl;
+        stream = s;
+        bound = true;
         return pl->alloc(&ptr, bytes);
     }
     void release_after(hipStream_t s) {
-        if (ptr && pool) pool->free_after(ptr, s);
+        if (ptr && pool) (void)pool->free_after(ptr, s);
         ptr = nullptr;
     }
+    void settle() { bound = false; }   // the caller waited for the stream: free at once
     template <class T> T *as() const { return static_cast<T *>(ptr); }
 };
+
+template <class... B> void settle_all(B &...b) { (b.settle(), ...); }
 
 class Server;   // serving loop (serve.cpp)
 

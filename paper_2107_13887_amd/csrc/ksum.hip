@@ -28,39 +28,11 @@
 //   * mixed precision: the pair arithmetic runs in FP32 on coordinates shifted to a per-workgroup
 //     origin (the workgroup's first point), the basis value is widened and accumulated in FP64.
 #include "basis.h"
-#include "internal.h"
+#include "ksum.h"
 
 namespace rbf {
+namespace ksum {
 namespace {
-
-constexpr int BLOCK = 256;
-constexpr int TILE = 256;
-
-struct KArgs {
-    int32_t n_levels;
-    int32_t n_split;
-    SumLevel lv[RBF_MAX_LEVELS];
-    const double *xc;               // [DIM][ld_ctrl]
-    const double *alpha;            // [DIM][ld_ctrl]
-    int64_t ld_ctrl;
-    const int32_t *work;            // reduced point list, or null for the identity
-    const int32_t *out_perm;        // resident geometry: output index of stored point w (-1: padding)
-    const int64_t *n_work_dev;      // device-side count (null: use n_work)
-    int64_t n_work;
-    const double *xp;
-    int64_t ld_p;
-    const double *dwall;
-    const double *base;
-    double sign;
-    double *out;
-    int64_t ld_out;
-    double *partial;                // [n_split][DIM][ld_part]
-    int64_t ld_part;
-    unsigned long long *pairs;      // evaluated (point, control) pairs are added here, or null
-    int64_t n_live;                 // rows from here on need no level (-1: every row may)
-    const double *block_box;        // resident geometry: box of every BOXROWS stored rows [n / BOXROWS][2 DIM], or null
-    const int32_t *order;           // resident geometry: row group of workgroup x (a permutation), or null: group x
-};
 
 // A control is dropped for a workgroup when its squared distance to the workgroup's box, in units
 // of R_l, is at least (1 + 1e-4)^2: every pair it would form then has eta > 1 and phi = 0, with
@@ -511,9 +483,6 @@ __global__ __launch_bounds__(BLOCK) void ksum_finalize(KArgs a)
 }
 
 // ---- wall-distance reduction ------------------------------------------------------------------
-constexpr int CHUNK = 4;                  // points per lane in the compaction
-constexpr int CBLK = BLOCK * CHUNK;       // points per compaction block
-
 __global__ __launch_bounds__(BLOCK) void reduce_count(const double *d, int64_t n, double dmax,
                                                      int32_t *counts)
 {
@@ -581,7 +550,7 @@ __global__ __launch_bounds__(BLOCK) void reduce_scatter(const double *d, int64_t
 }
 
 template <int DIM, int P, int BASIS>
-void launch_sum(const KArgs &a, dim3 grid, bool mixed, hipStream_t s)
+void launch_sum_t(const KArgs &a, dim3 grid, bool mixed, hipStream_t s)
 {
     if (mixed)
         hipLaunchKernelGGL((ksum_kernel<DIM, P, true, BASIS>), grid, dim3(BLOCK), 0, s, a);
@@ -592,8 +561,8 @@ void launch_sum(const KArgs &a, dim3 grid, bool mixed, hipStream_t s)
 template <int DIM, int BASIS>
 void launch_sum_p(const KArgs &a, dim3 grid, int P, bool mixed, hipStream_t s)
 {
-    if (P == 1) launch_sum<DIM, 1, BASIS>(a, grid, mixed, s);
-    else launch_sum<DIM, 2, BASIS>(a, grid, mixed, s);
+    if (P == 1) launch_sum_t<DIM, 1, BASIS>(a, grid, mixed, s);
+    else launch_sum_t<DIM, 2, BASIS>(a, grid, mixed, s);
 }
 
 template <int DIM>
@@ -607,132 +576,28 @@ void launch_sum_b(const KArgs &a, dim3 grid, int P, bool mixed, int32_t basis, h
     }
 }
 
-// Launch-shape overrides, read once per process (0: not set).
-struct ShapeEnv {
-    int P, blocks, max_split, split;
-    ShapeEnv()
-    {
-        auto get = [](const char *name) {
-            const char *v = getenv(name);
-            return v && *v ? atoi(v) : 0;
-        };
-        P = get("RBF_KSUM_P");
-        blocks = get("RBF_KSUM_BLOCKS");
-        max_split = get("RBF_KSUM_MAX_SPLIT");
-        split = get("RBF_KSUM_SPLIT");
-    }
-};
-
-const ShapeEnv &shape_env()
-{
-    static const ShapeEnv e;
-    return e;
-}
-
 }  // namespace
 
-rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
+void launch_sum(const KArgs &a, dim3 grid, int dim, int P, bool mixed, int32_t basis, hipStream_t s)
 {
-    const int DIM = pb.dim;
-    if (pb.n_p == 0) return RBF_OK;
-    KArgs a{};
-    a.n_live = -1;
-    a.n_levels = pb.n_levels;
-    int64_t nc_max = 0;
-    double dmax = 0.0;
-    for (int l = 0; l < pb.n_levels; ++l) {
-        a.lv[l] = pb.lv[l];
-        nc_max = std::max<int64_t>(nc_max, pb.lv[l].c_end - pb.lv[l].c_begin);
-        dmax = std::max(dmax, pb.lv[l].D);
-    }
-    a.xc = pb.xc;
-    a.alpha = pb.alpha;
-    a.ld_ctrl = pb.ld_ctrl;
-    a.xp = pb.xp;
-    a.ld_p = pb.n_p;
-    a.dwall = pb.dwall;
-    a.base = pb.base;
-    a.sign = pb.sign;
-    a.out = pb.out;
-    a.ld_out = pb.ld_out ? pb.ld_out : pb.n_p;
-    a.n_work = pb.n_p;
-
-    DevBuf work, nwork, partial, counts;
-    int64_t n_rows = pb.n_p;    // rows the kernel-sum grid covers
-    if (pb.dwall && pb.n_active >= 0) {
-        // Resident geometry: results go out through perm. The grid covers every point; the
-        // workgroups past the reduced prefix only write +0.0, so no separate zero-fill is
-        // launched.
-        a.out_perm = pb.perm;
-        a.n_live = pb.n_active;
-        a.block_box = pb.block_box;
-    } else if (pb.dwall) {
-        RBF_TRY(nwork.get(ctx->pool.get(), sizeof(int64_t)));
-        {
-            const int64_t nb = (pb.n_p + CBLK - 1) / CBLK;
-            RBF_TRY(work.get(ctx->pool.get(), sizeof(int32_t) * pb.n_p));
-            RBF_TRY(counts.get(ctx->pool.get(), sizeof(int32_t) * nb));
-            hipLaunchKernelGGL(reduce_count, dim3((unsigned)nb), dim3(BLOCK), 0, s, pb.dwall, pb.n_p,
-                               dmax, counts.as<int32_t>());
-            hipLaunchKernelGGL(reduce_scatter, dim3((unsigned)nb), dim3(BLOCK), 0, s, pb.dwall, pb.n_p,
-                               dmax, counts.as<const int32_t>(), nwork.as<int64_t>(), work.as<int32_t>(),
-                               pb.out, DIM);
-            a.work = work.as<int32_t>();
-        }
-        RBF_HIP(hipGetLastError());
-        a.n_work_dev = nwork.as<int64_t>();
-    }
-
-    // Launch shape: P points per lane; split the control lists when there are too few blocks.
-    // The FP32 pair form is compiled in when some level asks for it.
-    bool mixed = false;
-    for (int l = 0; l < pb.n_levels; ++l) mixed |= pb.lv[l].fp32 != 0;
-    // Two points per lane share every control read from LDS; one point per lane gives twice the
-    // workgroups, which balances better when there are few blocks (the cost of a block varies
-    // with the number of controls near it).
-    const ShapeEnv &env = shape_env();
-    int P = env.P ? env.P : (n_rows < (int64_t)8 * ctx->n_cu * VBLOCK ? 1 : 2);
-    if (P != 1 && P != 2) P = 2;
-    const int64_t nbx = (n_rows + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
-    const int64_t target = env.blocks > 0 ? env.blocks : (int64_t)8 * ctx->n_cu;
-    // Split only while every split keeps at least 128 controls: a split re-reads the points and
-    // writes partial sums, which pays only when it turns a ragged last round of waves into many.
-    int S = (int)std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, nc_max / 128));
-    S = std::min(S, env.max_split > 0 ? env.max_split : 64);
-    if (env.split > 0) S = env.split;
-    a.n_split = S;
-    // Resident geometry: workgroups take the row groups heaviest first, dealt across the compute
-    // units (RBF_KSUM_ORDER=0: stored order).
-    if (pb.geom) {
-        const char *e = getenv("RBF_KSUM_ORDER");
-        if (!(e && e[0] == '0')) RBF_TRY(resident_order(ctx, *pb.geom, pb, P, nbx, s, &a.order));
-    }
-    if (S > 1) {
-        RBF_TRY(partial.get(ctx->pool.get(), sizeof(double) * (size_t)S * DIM * n_rows));
-        a.partial = partial.as<double>();
-        a.ld_part = n_rows;
-    }
-    const dim3 grid((unsigned)nbx, (unsigned)S);
-    const char *name = pb.dwall ? (mixed ? "volume_ksum_mixed" : "volume_ksum_fp64")
-                                : (mixed ? "surface_ksum_mixed" : "surface_ksum_fp64");
-    a.pairs = ctx->timers.counter(name);
-    hipEvent_t t0;
-    ctx->timers.begin(&t0, s);
-    if (DIM == 2) launch_sum_b<2>(a, grid, P, mixed, pb.basis, s);
-    else launch_sum_b<3>(a, grid, P, mixed, pb.basis, s);
-    RBF_HIP(hipGetLastError());
-    ctx->timers.end(name, t0, s);
-    if (S > 1) {
-        const int gf = (int)std::min<int64_t>((n_rows + BLOCK - 1) / BLOCK, 8192);
-        if (DIM == 2) hipLaunchKernelGGL(ksum_finalize<2>, dim3(gf), dim3(BLOCK), 0, s, a);
-        else hipLaunchKernelGGL(ksum_finalize<3>, dim3(gf), dim3(BLOCK), 0, s, a);
-        RBF_HIP(hipGetLastError());
-    }
-    work.release_after(s);
-    counts.release_after(s);
-    nwork.release_after(s);
-    partial.release_after(s);
-    return RBF_OK;
+    if (dim == 2) launch_sum_b<2>(a, grid, P, mixed, basis, s);
+    else launch_sum_b<3>(a, grid, P, mixed, basis, s);
 }
 
+void launch_finalize(const KArgs &a, int dim, int blocks, hipStream_t s)
+{
+    if (dim == 2) hipLaunchKernelGGL(ksum_finalize<2>, dim3(blocks), dim3(BLOCK), 0, s, a);
+    else hipLaunchKernelGGL(ksum_finalize<3>, dim3(blocks), dim3(BLOCK), 0, s, a);
+}
+
+void launch_reduce(const double *d, int64_t n, double dmax, int32_t *counts, int64_t *n_work,
+                   int32_t *work, double *out, int32_t dim, hipStream_t s)
+{
+    const int64_t nb = (n + CBLK - 1) / CBLK;
+    hipLaunchKernelGGL(reduce_count, dim3((unsigned)nb), dim3(BLOCK), 0, s, d, n, dmax, counts);
+    hipLaunchKernelGGL(reduce_scatter, dim3((unsigned)nb), dim3(BLOCK), 0, s, d, n, dmax,
+                       (const int32_t *)counts, n_work, work, out, dim);
+}
+
+}  // namespace ksum
 }  // namespace rbf

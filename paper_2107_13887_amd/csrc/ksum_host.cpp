@@ -1,0 +1,138 @@
+// Host planner of the kernel sums (ksum.hip): per-call volume reduction, launch shape (points per
+// lane, control-list splits), the resident geometry's row-group order, timers and the
+// evaluated-pair counter.
+#include <algorithm>
+#include <cstdlib>
+
+#include "ksum.h"
+
+namespace rbf {
+
+using namespace ksum;
+
+namespace {
+
+// Launch-shape overrides, read once per process (0: not set).
+struct ShapeEnv {
+    int P, blocks, max_split, split;
+    ShapeEnv()
+    {
+        auto get = [](const char *name) {
+            const char *v = getenv(name);
+            return v && *v ? atoi(v) : 0;
+        };
+        P = get("RBF_KSUM_P");
+        blocks = get("RBF_KSUM_BLOCKS");
+        max_split = get("RBF_KSUM_MAX_SPLIT");
+        split = get("RBF_KSUM_SPLIT");
+    }
+};
+
+const ShapeEnv &shape_env()
+{
+    static const ShapeEnv e;
+    return e;
+}
+
+}  // namespace
+
+rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
+{
+    const int DIM = pb.dim;
+    if (pb.n_p == 0) return RBF_OK;
+    KArgs a{};
+    a.n_live = -1;
+    a.n_levels = pb.n_levels;
+    int64_t nc_max = 0;
+    double dmax = 0.0;
+    for (int l = 0; l < pb.n_levels; ++l) {
+        a.lv[l] = pb.lv[l];
+        nc_max = std::max<int64_t>(nc_max, pb.lv[l].c_end - pb.lv[l].c_begin);
+        dmax = std::max(dmax, pb.lv[l].D);
+    }
+    a.xc = pb.xc;
+    a.alpha = pb.alpha;
+    a.ld_ctrl = pb.ld_ctrl;
+    a.xp = pb.xp;
+    a.ld_p = pb.n_p;
+    a.dwall = pb.dwall;
+    a.base = pb.base;
+    a.sign = pb.sign;
+    a.out = pb.out;
+    a.ld_out = pb.ld_out ? pb.ld_out : pb.n_p;
+    a.n_work = pb.n_p;
+
+    DevBuf work, nwork, partial, counts;
+    int64_t n_rows = pb.n_p;    // rows the kernel-sum grid covers
+    if (pb.dwall && pb.n_active >= 0) {
+        // Resident geometry: results go out through perm. The grid covers every point; the
+        // workgroups past the reduced prefix only write +0.0, so no separate zero-fill is
+        // launched.
+        a.out_perm = pb.perm;
+        a.n_live = pb.n_active;
+        a.block_box = pb.block_box;
+    } else if (pb.dwall) {
+        RBF_TRY(nwork.get(ctx->pool.get(), sizeof(int64_t), s));
+        {
+            const int64_t nb = (pb.n_p + CBLK - 1) / CBLK;
+            RBF_TRY(work.get(ctx->pool.get(), sizeof(int32_t) * pb.n_p, s));
+            RBF_TRY(counts.get(ctx->pool.get(), sizeof(int32_t) * nb, s));
+            launch_reduce(pb.dwall, pb.n_p, dmax, counts.as<int32_t>(), nwork.as<int64_t>(), work.as<int32_t>(),
+                          pb.out, DIM, s);
+            a.work = work.as<int32_t>();
+        }
+        RBF_HIP(hipGetLastError());
+        a.n_work_dev = nwork.as<int64_t>();
+    }
+
+    // Launch shape: P points per lane; split the control lists when there are too few blocks.
+    // The FP32 pair form is compiled in when some level asks for it.
+    bool mixed = false;
+    for (int l = 0; l < pb.n_levels; ++l) mixed |= pb.lv[l].fp32 != 0;
+    // Two points per lane share every control read from LDS; one point per lane gives twice the
+    // workgroups, which balances better when there are few blocks (the cost of a block varies
+    // with the number of controls near it).
+    const ShapeEnv &env = shape_env();
+    int P = env.P ? env.P : (n_rows < (int64_t)8 * ctx->n_cu * VBLOCK ? 1 : 2);
+    if (P != 1 && P != 2) P = 2;
+    const int64_t nbx = (n_rows + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
+    const int64_t target = env.blocks > 0 ? env.blocks : (int64_t)8 * ctx->n_cu;
+    // Split only while every split keeps at least 128 controls: a split re-reads the points and
+    // writes partial sums, which pays only when it turns a ragged last round of waves into many.
+    int S = (int)std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, nc_max / 128));
+    S = std::min(S, env.max_split > 0 ? env.max_split : 64);
+    if (env.split > 0) S = env.split;
+    a.n_split = S;
+    // Resident geometry: workgroups take the row groups heaviest first, dealt across the compute
+    // units (RBF_KSUM_ORDER=0: stored order).
+    if (pb.geom) {
+        const char *e = getenv("RBF_KSUM_ORDER");
+        if (!(e && e[0] == '0')) RBF_TRY(resident_order(ctx, *pb.geom, pb, P, nbx, s, &a.order));
+    }
+    if (S > 1) {
+        RBF_TRY(partial.get(ctx->pool.get(), sizeof(double) * (size_t)S * DIM * n_rows, s));
+        a.partial = partial.as<double>();
+        a.ld_part = n_rows;
+    }
+    const dim3 grid((unsigned)nbx, (unsigned)S);
+    const char *name = pb.dwall ? (mixed ? "volume_ksum_mixed" : "volume_ksum_fp64")
+                                : (mixed ? "surface_ksum_mixed" : "surface_ksum_fp64");
+    a.pairs = ctx->timers.counter(name);
+    hipEvent_t t0;
+    ctx->timers.begin(&t0, s);
+    launch_sum(a, grid, DIM, P, mixed, pb.basis, s);
+    RBF_HIP(hipGetLastError());
+    ctx->timers.end(name, t0, s);
+    if (S > 1) {
+        const int gf = (int)std::min<int64_t>((n_rows + BLOCK - 1) / BLOCK, 8192);
+        launch_finalize(a, DIM, gf, s);
+        RBF_HIP(hipGetLastError());
+    }
+    work.release_after(s);
+    counts.release_after(s);
+    nwork.release_after(s);
+    partial.release_after(s);
+    return RBF_OK;
+}
+
+}  // namespace rbf

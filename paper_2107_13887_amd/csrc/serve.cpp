@@ -340,17 +340,21 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     const int64_t n_pad = nb * VBLOCK;
     g.n_pad = n_pad;
     g.block_dmin.clear();
-    RBF_TRY(g.xs.get(pool, sizeof(double) * DIM * n_s));
+    RBF_TRY(g.xs.get(pool, sizeof(double) * DIM * n_s, s));
     RBF_HIP(hipMemcpyAsync(g.xs.ptr, xs, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
-    RBF_TRY(g.xv_sorted.get(pool, sizeof(double) * DIM * std::max<int64_t>(1, n_pad)));
-    RBF_TRY(g.d_sorted.get(pool, sizeof(double) * std::max<int64_t>(1, n_pad)));
-    RBF_TRY(g.perm.get(pool, sizeof(int32_t) * std::max<int64_t>(1, n_pad)));
+    RBF_TRY(g.xv_sorted.get(pool, sizeof(double) * DIM * std::max<int64_t>(1, n_pad), s));
+    RBF_TRY(g.d_sorted.get(pool, sizeof(double) * std::max<int64_t>(1, n_pad), s));
+    RBF_TRY(g.perm.get(pool, sizeof(int32_t) * std::max<int64_t>(1, n_pad), s));
     g.bytes = sizeof(double) * (DIM * (n_s + n_pad) + n_pad + 2 * DIM * (n_pad / BOXROWS)) + sizeof(int32_t) * n_pad;
-    if (n_v == 0) return RBF_OK;
+    if (n_v == 0) {
+        RBF_HIP(hipStreamSynchronize(s));
+        settle_all(g.xs, g.xv_sorted, g.d_sorted, g.perm);
+        return RBF_OK;
+    }
     DevBuf dtmp, part, k0, k1, i0, i1, hist, bmin, border;
     const double *d = dwall;
     if (!d) {
-        RBF_TRY(dtmp.get(pool, sizeof(double) * n_v));
+        RBF_TRY(dtmp.get(pool, sizeof(double) * n_v, s));
         hipLaunchKernelGGL(geo_walldist<DIM>, dim3((unsigned)((n_v + 255) / 256)), dim3(256), 0, s,
                            g.xs.as<double>(), n_s, xv, n_v, dtmp.as<double>());
         RBF_HIP(hipGetLastError());
@@ -358,7 +362,7 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     }
     // Z-order keys over the volume's bounding box.
     const int gb = (int)std::min<int64_t>((n_v + 255) / 256, 512);
-    RBF_TRY(part.get(pool, sizeof(double) * 2 * DIM * gb));
+    RBF_TRY(part.get(pool, sizeof(double) * 2 * DIM * gb, s));
     hipLaunchKernelGGL(geo_bbox<DIM>, dim3(gb), dim3(256), 0, s, xv, n_v, part.as<double>());
     std::vector<double> ph((size_t)2 * DIM * gb);
     RBF_HIP(hipMemcpyAsync(ph.data(), part.ptr, sizeof(double) * ph.size(), hipMemcpyDeviceToHost, s));
@@ -374,15 +378,15 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
         box.lo[k] = lo;
         box.scale[k] = hi > lo ? (DIM == 2 ? 65536.0 : 1024.0) / (hi - lo) : 0.0;
     }
-    RBF_TRY(k0.get(pool, sizeof(uint32_t) * n_v));
-    RBF_TRY(k1.get(pool, sizeof(uint32_t) * n_v));
-    RBF_TRY(i0.get(pool, sizeof(int32_t) * n_v));
-    RBF_TRY(i1.get(pool, sizeof(int32_t) * n_v));
+    RBF_TRY(k0.get(pool, sizeof(uint32_t) * n_v, s));
+    RBF_TRY(k1.get(pool, sizeof(uint32_t) * n_v, s));
+    RBF_TRY(i0.get(pool, sizeof(int32_t) * n_v, s));
+    RBF_TRY(i1.get(pool, sizeof(int32_t) * n_v, s));
     hipLaunchKernelGGL(geo_morton<DIM>, dim3((unsigned)((n_v + 255) / 256)), dim3(256), 0, s, xv, n_v, box,
                        k0.as<uint32_t>(), i0.as<int32_t>());
     // Stable LSD radix sort of (key, index), four 8-bit passes.
     const int64_t nblk = (n_v + SORT_BLK - 1) / SORT_BLK;
-    RBF_TRY(hist.get(pool, sizeof(int32_t) * NBUCKET * nblk));
+    RBF_TRY(hist.get(pool, sizeof(int32_t) * NBUCKET * nblk, s));
     DevBuf *kin = &k0, *kout = &k1, *iin = &i0, *iout = &i1;
     for (int shift = 0; shift < 32; shift += 8) {
         hipLaunchKernelGGL(radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, kin->as<const uint32_t>(), n_v, shift,
@@ -397,7 +401,7 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     RBF_HIP(hipGetLastError());
     // Blocks of VBLOCK points in Z order, stored by increasing smallest wall distance: the
     // points of any support distance D then lie in a prefix of whole blocks.
-    RBF_TRY(bmin.get(pool, sizeof(double) * nb));
+    RBF_TRY(bmin.get(pool, sizeof(double) * nb, s));
     hipLaunchKernelGGL(geo_blockmin, dim3((unsigned)nb), dim3(256), 0, s, d, iin->as<const int32_t>(), n_v,
                        bmin.as<double>());
     std::vector<double> bm(nb);
@@ -408,18 +412,19 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return bm[a] < bm[b]; });
     g.block_dmin.resize(nb);
     for (int64_t r = 0; r < nb; ++r) g.block_dmin[r] = bm[order[r]];
-    RBF_TRY(border.get(pool, sizeof(int32_t) * nb));
+    RBF_TRY(border.get(pool, sizeof(int32_t) * nb, s));
     RBF_HIP(hipMemcpyAsync(border.ptr, order.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(geo_gather<DIM>, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, s,
                        border.as<const int32_t>(), iin->as<const int32_t>(), d, xv, n_v, n_pad,
                        g.perm.as<int32_t>(), g.d_sorted.as<double>(), g.xv_sorted.as<double>());
     hipLaunchKernelGGL(geo_blocksort<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<int32_t>(),
                        g.d_sorted.as<double>(), g.xv_sorted.as<double>(), n_pad);
-    RBF_TRY(g.block_box.get(pool, sizeof(double) * 2 * DIM * (n_pad / BOXROWS)));
+    RBF_TRY(g.block_box.get(pool, sizeof(double) * 2 * DIM * (n_pad / BOXROWS), s));
     hipLaunchKernelGGL(geo_blockbox<DIM>, dim3((unsigned)(n_pad / 256)), dim3(256), 0, s, g.perm.as<const int32_t>(),
                        g.xv_sorted.as<const double>(), n_pad, g.block_box.as<double>());
     RBF_HIP(hipGetLastError());
     RBF_HIP(hipStreamSynchronize(s));
+    settle_all(g.xs, g.xv_sorted, g.d_sorted, g.perm, g.block_box, dtmp, part, k0, k1, i0, i1, hist, bmin, border);
     return RBF_OK;
 }
 
@@ -528,7 +533,7 @@ rbf_status resident_order(rbf_ctx ctx, Geometry &g, const SumProblem &pb, int P,
         lv.c_end[l] = pb.xc ? pb.lv[l].c_end : pb.lv[l].c_begin;
     }
     DevBuf bw;
-    RBF_TRY(bw.get(ctx->pool.get(), sizeof(double) * (size_t)n_groups));
+    RBF_TRY(bw.get(ctx->pool.get(), sizeof(double) * (size_t)n_groups, s));
     if (g.dim == 2)
         hipLaunchKernelGGL(geo_group_weight<2>, dim3((unsigned)n_groups), dim3(256), 0, s, pb.xc, pb.ld_ctrl,
                            g.block_box.as<const double>(), g.d_sorted.as<const double>(), rows, lv, bw.as<double>());
@@ -539,6 +544,7 @@ rbf_status resident_order(rbf_ctx ctx, Geometry &g, const SumProblem &pb, int P,
     std::vector<double> wt((size_t)n_groups);
     RBF_HIP(hipMemcpyAsync(wt.data(), bw.ptr, sizeof(double) * (size_t)n_groups, hipMemcpyDeviceToHost, s));
     RBF_HIP(hipStreamSynchronize(s));
+    bw.settle();
     // Heaviest first (stored order among equals), dealt to the compute units back and forth:
     // workgroup x runs on unit x mod n_cu, every workgroup resident at once.
     std::vector<int32_t> rank((size_t)n_groups);
@@ -775,9 +781,9 @@ rbf_status Server::run(Req &q, hipStream_t s)
     rbf_ctrl_set *cs = q.r.out;
     DevBuf bi, bx, ba;
     if (!cs) {
-        RBF_TRY(bi.get(ctx_->pool.get(), sizeof(int64_t) * cap));
-        RBF_TRY(bx.get(ctx_->pool.get(), sizeof(double) * dim * cap));
-        RBF_TRY(ba.get(ctx_->pool.get(), sizeof(double) * dim * cap));
+        RBF_TRY(bi.get(ctx_->pool.get(), sizeof(int64_t) * cap, s));
+        RBF_TRY(bx.get(ctx_->pool.get(), sizeof(double) * dim * cap, s));
+        RBF_TRY(ba.get(ctx_->pool.get(), sizeof(double) * dim * cap, s));
         local.capacity = cap;
         local.ctrl_idx = bi.as<int64_t>();
         local.xc = bx.as<double>();
@@ -820,6 +826,7 @@ rbf_status Server::run(Req &q, hipStream_t s)
     pb.basis = p.basis;
     RBF_TRY(run_kernel_sum(ctx_, pb, s));
     RBF_HIP(hipStreamSynchronize(s));
+    settle_all(bi, bx, ba);
     // Remember the control sets for the next icing step on this geometry.
     std::vector<int64_t> all(cs->level_off[p.n_levels]);
     if (!all.empty())
@@ -901,6 +908,7 @@ rbf_status rbf_geom_create(rbf_ctx ctx, int32_t dim, int64_t n_s, const double *
     rbf_status st = dim == 2 ? build_geometry<2>(ctx, *g, xs, xv, dwall, s)
                              : build_geometry<3>(ctx, *g, xs, xv, dwall, s);
     (void)hipStreamSynchronize(s);
+    settle_all(g->xs, g->xv_sorted, g->d_sorted, g->perm, g->block_box);   // the stream is idle
     (void)hipStreamDestroy(s);
     if (st < 0) return st;
     rbf_geom h = reinterpret_cast<rbf_geom>(g.get());

@@ -7,6 +7,7 @@ present, the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 import re
@@ -121,6 +122,26 @@ _SIGS = {
 }
 
 _lib = None
+_live_ctx: set = set()   # contexts created through this binding and not yet destroyed
+
+
+def _unload_at_exit() -> None:
+    """Unload the library at interpreter exit, while the HIP runtime is still whole.
+
+    hipcc registers each translation unit's module destructor (the unregistration of its GPU
+    code object) with atexit() when the library is loaded. exit() runs such handlers in reverse
+    order of registration, so any handler registered after the load (the HIP runtime's or a
+    profiler's finalisation, when they initialise after this library was loaded) runs first, and
+    the unregistration then calls into a runtime that is already torn down. dlclose() runs the
+    library's handlers at once instead; Python's own atexit callbacks run before any C exit
+    handler. Skipped while a context is alive (its worker threads run library code)."""
+    global _lib
+    if _lib is None or _live_ctx:
+        return
+    import _ctypes
+
+    handle, _lib = _lib._handle, None
+    _ctypes.dlclose(handle)
 
 
 def header_functions() -> List[str]:
@@ -142,6 +163,7 @@ def lib() -> ctypes.CDLL:
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        atexit.register(_unload_at_exit)
     return _lib
 
 
@@ -207,11 +229,13 @@ def _dev(t, name: str, dim: Optional[int] = None, n: Optional[int] = None, allow
 def rbf_ctx_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
     h = _vp()
     _check(lib().rbf_ctx_create(device, hbm_budget_bytes, ctypes.byref(h)), "rbf_ctx_create")
+    _live_ctx.add(h.value)
     return h.value
 
 
 def rbf_ctx_destroy(ctx: int) -> None:
     _check(lib().rbf_ctx_destroy(ctx), "rbf_ctx_destroy")
+    _live_ctx.discard(ctx)
 
 
 def rbf_ctx_bytes_in_use(ctx: int) -> int:
