@@ -3,20 +3,23 @@
 
 One step = the whole path on one synthetic deformation: multi-level greedy selection of the
 control points on the surface (rbf_greedy_select) followed by the wall-distance-reduced volume
-update (rbf_volume_update). Inputs are resident in HBM before the timed region starts.
+update on the resident geometry (rbf_geom_volume_update). Inputs are resident in HBM before the
+timed region starts. Default workload: the 3D iced swept wing (80,000 surface points, 4,000,000
+volume points, three levels, FP64), the largest configuration that fits one GPU.
 
-Headline value: RBF evaluations per second of the volume update, i.e. the number of
-(reduced volume point, control point) pairs sum_l n_{D_l} N_{c,l} divided by the device time of
-the volume-update calls (hipEvents on the launch stream). The kernel skips the controls whose
-support misses a block of points (phi = 0 there), so it computes fewer pairs than that count;
-the roofline fraction is taken on the pairs it actually computes (counted on the device). The geometry is made resident once
-before the timed region (rbf_geom_create: volume stored in wall-distance order), so each step's
-volume reduction is a prefix (rbf_geom_volume_update); the plain call on the unsorted volume
-(rbf_volume_update, with its per-call compaction) is reported beside it. Also reported: greedy time-to-eps,
-the roofline fraction of the volume kernel-sum launch (VALU issue bound), and the FP64 CPU oracle
-timed on this machine's host cores on the same workload.
+Headline value: in-support RBF evaluations per second of the volume update, i.e. the
+(reduced volume point, control point) pairs of the same level with psi(d / D_l) > 0 and
+phi(||x_v - x_c|| / R_l) > 0, counted exactly on the host (KD-tree pair count), divided by the
+device time of the volume-update calls (hipEvents on the launch stream). Beside it: the dense
+count sum_l n_{D_l} N_{c,l} and the pairs the kernel actually evaluates after its per-workgroup
+compact-support cull (device counter). The roofline fraction of the volume kernel launch (VALU
+issue bound) is taken on the in-support pairs. Also reported: greedy time-to-eps and its
+Newton-basis stream against HBM peak, the plain call on the unsorted volume, the FP32 pair form
+and the guarded mixed form against FP64 and the oracle, further workloads (the 2D multi-level
+airfoil; the bent and twisted wing in mixed precision with its mesh validity), a reduced serving
+mix, and the FP64 CPU oracle timed on this machine's host cores on the same workload.
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload cfg1] [--precision fp64]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 3] [--workload cfg2] [--precision fp64]
 """
 import argparse
 import json
@@ -28,9 +31,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-METRIC = ("RBF evals/s (volume update: reduced-volume points x control points per second; pairs "
-          "outside the compact support are skipped, not computed), greedy time-to-eps, p50/p99 "
-          "request latency")
+METRIC = ("RBF evals/s (volume update: in-support reduced-volume point x control point pairs, "
+          "psi > 0 and phi > 0, per second), greedy time-to-eps, p50/p99 request latency")
 VALU_LANE_OPS = 256 * 64 * 2.4e9          # 256 CUs x 64 lanes x 2.4 GHz
 HBM_PEAK_GBS = 8000.0                     # MI355X HBM3E
 # Minimal VALU issue slots per (point, control) pair with the Wendland C2 basis: dim subtractions,
@@ -77,17 +79,25 @@ def build_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+# The device code of the volume kernel sum: its kernels and launch wrappers, their argument block
+# and the basis functions they inline. The host planner (ksum_host.cpp) is left out.
+KERNEL_SOURCES = ("ksum.hip", "ksum.h", "basis.h")
+
+
 def kernel_source_hash():
-    """Hash of the kernel-sum source with comments and white space removed, so that a counter
-    summary stays matched to its kernel through edits of the comments only."""
+    """Hash of the kernel-sum device sources with comments and white space removed, so that a
+    counter summary stays matched to its kernel through edits of the comments only."""
     import hashlib
     import re
 
-    with open(os.path.join(ROOT, "paper_2107_13887_amd", "csrc", "ksum.hip")) as f:
-        src = f.read()
-    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
-    src = re.sub(r"//[^\n]*", " ", src)
-    return hashlib.sha256("".join(src.split()).encode()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2107_13887_amd", "csrc", name)) as f:
+            src = f.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update("".join(src.split()).encode())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, precision):
@@ -112,59 +122,6 @@ def _omp():
         return ctypes.CDLL("libgomp.so.1")
     except OSError:
         return None
-
-
-def cpu_baseline(w, cs, radius, D, off, basis, big, budget_s=12.0):
-    """The FP64 oracle timed on this machine's host cores, on a bounded sample of the same
-    workload: the volume update of the step's control sets over the reduced volume (all of it,
-    or a seeded subset when one pass would be long), repeated for about budget_s seconds; the same
-    on one thread for a short while; and the oracle's whole greedy where it is affordable."""
-    import numpy as np
-
-    import oracle
-
-    o = oracle.get()
-    xc = cs.xc[:, : cs.total].cpu().numpy()
-    al = cs.alpha[:, : cs.total].cpu().numpy()
-    inside = np.flatnonzero(w.dwall < max(D))
-    per_point = np.zeros(w.n_v)
-    for l in range(len(radius)):
-        per_point += (w.dwall < D[l]) * (off[l + 1] - off[l])
-    rng = np.random.default_rng(5)
-    n_pick = int(min(inside.size, max(1000, 2e9 / max(1.0, per_point[inside].mean()))))
-    pick = np.sort(rng.choice(inside, n_pick, replace=False)) if n_pick < inside.size else inside
-    xv, dwp = np.ascontiguousarray(w.xv[:, pick]), np.ascontiguousarray(w.dwall[pick])
-    pairs = float(per_point[pick].sum())
-    omp = _omp()
-    cores = int(omp.omp_get_max_threads()) if omp else int(os.environ.get("OMP_NUM_THREADS", 1))
-
-    def timed(fn, budget):
-        reps, t = 0, 0.0
-        while t < budget and reps < 1000:
-            t0 = time.perf_counter()
-            fn()
-            t += time.perf_counter() - t0
-            reps += 1
-        return reps, t
-
-    vol = lambda pts=xv, d=dwp: o.volume(radius, D, off, xc, al, pts, d, basis=basis)
-    reps, t = timed(vol, budget_s)
-    out = {"value": pairs * reps / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
-           "sample": f"volume update of the step's {cs.total} control points over {pick.size} of the "
-                     f"{inside.size} reduced-volume points ({pairs:.3g} pairs), {reps} repetitions in "
-                     f"{t:.1f} s"}
-    if omp:
-        sub = pick[: max(1, pick.size // max(1, cores))]
-        omp.omp_set_num_threads(1)
-        r1, t1 = timed(lambda: vol(np.ascontiguousarray(w.xv[:, sub]), np.ascontiguousarray(w.dwall[sub])), 2.0)
-        omp.omp_set_num_threads(cores)
-        out["single_thread_value"] = float(per_point[sub].sum()) * r1 / t1
-    if not big:
-        g = lambda: o.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
-                             seeds=w.seeds, basis=basis)
-        rg, tg = timed(g, 3.0)
-        out["greedy_time_to_eps_s"] = tg / rg
-    return out
 
 
 def serving_replay(ctx, geoms, reqs, time_scale=1.0, compare=True):
@@ -293,46 +250,46 @@ def _normwise(got, ref):
             "normwise": float(err.max() / scale) if scale > 0 else None}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cfg1",
-                    help="cfg0..cfg3, sine2d, sine3d (one deformation per step), or cfg4 (serving mix)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--basis", default="c2", choices=["c0", "c2", "c4", "c6"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-geometries", type=int, default=16,
-                    help="geometries of the reduced serving mix replayed after the main timing (0: skip)")
-    ap.add_argument("--serve-scale", type=float, default=0.25,
-                    help="size scale of the reduced serving mix")
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="also run one plain device copy of this many MiB (HBM counter calibration)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
+def in_support_pairs(w, radius, D, off, xc):
+    """Exact count of the (reduced volume point, control point) pairs of one volume update that lie
+    inside the compact support, level by level: d_v < D_l (psi > 0, Section 4) and
+    ||x_v - x_c|| < R_l (phi > 0, eq. (2)). A KD-tree pair count on the host, independent of the
+    GPU path; pairs exactly at distance R_l (phi = 0) are left out."""
     import numpy as np
+    from scipy.spatial import cKDTree
+
+    trees, total, per_level = {}, 0, []
+    for l in range(len(radius)):
+        lo, hi = int(off[l]), int(off[l + 1])
+        if hi <= lo:
+            per_level.append(0)
+            continue
+        key = float(D[l])
+        if key not in trees:
+            trees[key] = cKDTree(np.ascontiguousarray(w.xv[:, w.dwall < D[l]].T))
+        n = int(cKDTree(np.ascontiguousarray(xc[:, lo:hi].T)).count_neighbors(
+            trees[key], np.nextafter(float(radius[l]), 0.0)))
+        per_level.append(n)
+        total += n
+    return total, per_level
+
+
+def run_workload(ctx, name, precision, basis, steps, warmup):
+    """Greedy selection plus resident volume update of one workload, timed; returns the raw
+    measurements the record is built from."""
     import torch
 
-    import oracle
     from paper_2107_13887_amd import rbfdef
 
-    if args.workload == "cfg4":
-        return serve_main(args)
     t0 = time.perf_counter()
-    w, desc = build_workload(args.workload)
+    w, desc = build_workload(name)
     log(f"bench: workload {w.name} built in {time.perf_counter() - t0:.1f}s")
-    big = w.n_s * w.cap_total() > 5e7       # the oracle's whole greedy would take minutes
     dev = torch.device("cuda:0")
+    m = {"w": w, "desc": desc, "precision": precision}
     xs = torch.from_numpy(w.xs).to(dev)
     ds = torch.from_numpy(w.ds).to(dev)
     xv = torch.from_numpy(w.xv).to(dev)
     dw = torch.from_numpy(w.dwall).to(dev)
-    ctx = rbfdef.rbf_ctx_create(0)
     stream = torch.cuda.current_stream()
     # Setup, outside the timed region: the geometry (surface, volume, wall distances) becomes
     # resident once, as across successive icing steps.
@@ -349,66 +306,207 @@ def main():
     def step():
         g0 = time.perf_counter()
         cs = rbfdef.rbf_greedy_select(ctx, xs, ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
-                                      seeds=w.seeds, precision=args.precision, want_residual=False,
-                                      basis=args.basis)
+                                      seeds=w.seeds, precision=precision, want_residual=False,
+                                      basis=basis)
         g1 = time.perf_counter()
         radius, D, off = supports(cs)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         rbfdef.rbf_geom_volume_update(ctx, geom, radius, D, off, cs.xc, cs.alpha, dv,
-                                      precision=args.precision, basis=args.basis)
+                                      precision=precision, basis=basis)
         e1.record(stream)
         return cs, g1 - g0, (e0, e1)
 
-    if args.copy_calibration_mib > 0:
-        n = args.copy_calibration_mib * (1 << 20) // 8
-        src = torch.ones(n, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    for i in range(args.warmup):
+    for i in range(warmup):
         cs, _, _ = step()
         torch.cuda.synchronize()
-        log(f"bench: warmup {i + 1}/{args.warmup} done ({cs.total} control points)")
+        log(f"bench: {name}: warmup {i + 1}/{warmup} done ({cs.total} control points)")
     rbfdef.rbf_ctx_set_timing(ctx, True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     greedy_t, events = [], []
-    for i in range(args.steps):
+    for i in range(steps):
         cs, tg, ev = step()
         greedy_t.append(tg)
         events.append(ev)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     vol_ms = [a.elapsed_time(b) for a, b in events]
-    kname = "volume_ksum_" + args.precision
+    kname = "volume_ksum_" + precision
     k_ms, k_n = rbfdef.rbf_ctx_kernel_time(ctx, kname)
     rbfdef.rbf_ctx_set_timing(ctx, False)
-    log(f"bench: {args.steps} steps in {wall:.3f}s")
+    log(f"bench: {name}: {steps} steps in {wall:.3f}s")
     radius, D, off = supports(cs)
     vol_call = lambda prec: rbfdef.rbf_geom_volume_update(ctx, geom, radius, D, off, cs.xc, cs.alpha, dv,
-                                                          precision=prec, basis=args.basis)
-    # Pairs the kernel computes per launch: one more, untimed launch with the device counter on.
+                                                          precision=prec, basis=basis)
+    # Pairs the kernel evaluates per launch: one more, untimed launch with the device counter on.
     rbfdef.rbf_ctx_set_timing(ctx, False, count_pairs=True)
-    vol_call(args.precision)
+    vol_call(precision)
     evaluated = float(rbfdef.rbf_ctx_kernel_pairs(ctx, kname))
     rbfdef.rbf_ctx_set_timing(ctx, False)
-    # Secondary: the plain call on the caller's (unsorted) volume, with its per-call compaction.
-    plain_ms = _median_ms(stream, lambda: rbfdef.rbf_volume_update(
-        ctx, radius, D, off, cs.xc, cs.alpha, xv, dw, precision=args.precision, basis=args.basis), 5)
-
     n_c = [off[l + 1] - off[l] for l in range(len(radius))]
     n_d = [int((w.dwall < D[l]).sum()) for l in range(len(radius))]
-    pairs = sum(n_d[l] * n_c[l] for l in range(len(radius)))
-    value = pairs * args.steps / (sum(vol_ms) / 1e3)
-    avg_kernel_s = (k_ms / k_n) / 1e3 if k_n else float("nan")
-    peak = VALU_LANE_OPS / min_slots(w.dim, args.basis, args.precision) / 1e9
-    achieved = evaluated / avg_kernel_s / 1e9
+    xcn = cs.xc[:, : cs.total].cpu().numpy()
+    in_sup, in_sup_l = in_support_pairs(w, radius, D, off, xcn)
+    m.update(dict(xs=xs, ds=ds, xv=xv, dw=dw, geom=geom, dv=dv, cs=cs, radius=radius, D=D, off=off,
+                  greedy_t=greedy_t, vol_ms=vol_ms, wall=wall, kname=kname, k_ms=k_ms, k_n=k_n,
+                  vol_call=vol_call, evaluated=evaluated, n_c=n_c, n_d=n_d,
+                  dense_pairs=sum(n_d[l] * n_c[l] for l in range(len(radius))),
+                  in_support=in_sup, in_support_per_level=in_sup_l, xcn=xcn,
+                  alpha=cs.alpha[:, : cs.total].cpu().numpy(), stream=stream))
+    return m
 
-    # Precision study on this step's control sets: the FP32 pair arithmetic (shifted local origin,
-    # FP64 accumulation) beside the FP64 path, and both against the FP64 oracle on sampled points.
+
+def volume_roofline(m, precision, basis, workload):
+    """Roofline of the dominant volume launch: in-support pairs per launch over the launch's
+    average device time (library hipEvents on the launch stream, timed region), against the
+    VALU-issue peak in pairs/s."""
+    w = m["w"]
+    avg_kernel_s = (m["k_ms"] / m["k_n"]) / 1e3 if m["k_n"] else float("nan")
+    peak = VALU_LANE_OPS / min_slots(w.dim, basis, precision) / 1e9
+    achieved = m["in_support"] / avg_kernel_s / 1e9
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
+            "frac": achieved / peak,
+            "frac_of_evaluated": m["evaluated"] / avg_kernel_s / 1e9 / peak,
+            "traffic": measured_traffic(workload, precision) if basis == "c2" else None,
+            "kernel": m["kname"], "kernel_avg_ms": avg_kernel_s * 1e3, "kernel_launches": m["k_n"],
+            "work_unit": "in-support (reduced volume point, control) pairs per launch (psi > 0 and "
+                         "phi > 0, counted exactly on the host); the kernel evaluates "
+                         f"{m['evaluated']:.4g} pairs per launch after its compact-support cull"}
+
+
+def greedy_block(m, basis):
+    """Greedy time-to-eps, iteration rate and the Newton-basis stream against HBM peak."""
+    w, cs = m["w"], m["cs"]
+    used = cs.n_levels_used
+    g_bytes = 0
+    for l in range(used):
+        k = m["n_c"][l] if l < len(m["n_c"]) else 0
+        g_bytes += 8 * w.n_s * (k * (k - 1) // 2) + k * w.n_s * (9 + 24 * w.dim)
+    g_time = statistics.median(m["greedy_t"])
+    return {
+        "greedy_time_to_eps_s": g_time,
+        "greedy_iterations": cs.n_iterations,
+        "greedy_iterations_per_s": cs.n_iterations / g_time,
+        "greedy_us_per_iteration": g_time / max(1, cs.n_iterations) * 1e6,
+        "greedy_roofline": {"bound": "hbm", "achieved": g_bytes / g_time / 1e9, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": g_bytes / g_time / 1e9 / HBM_PEAK_GBS,
+                            "algorithmic_bytes": g_bytes,
+                            "work_unit": "Newton-basis stream of every iteration (N_s x n read, one "
+                                         "column written, E and x_s), whole greedy call timed"},
+        "greedy_levels": [{"controls": m["n_c"][l] if l < len(m["n_c"]) else 0,
+                           "seconds": cs.level_seconds[l], "max_err_in": cs.level_in_max[l],
+                           "max_err_out": cs.level_max_err[l]} for l in range(used)],
+    }
+
+
+def golden_selection(w):
+    """The stored full selection of this workload (written by tests/golden/make_greedy_golden.py
+    from the oracle) when its input hash matches, else None."""
+    import numpy as np
+
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    try:
+        import make_greedy_golden as mg
+    finally:
+        sys.path.pop(0)
+    name = w.name.split("_")[0]
+    path = mg.path_for(name)
+    if not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    if str(z["input_sha"]) != mg.input_sha(w):
+        return None
+    return z
+
+
+def oracle_leg(m, basis, big, budget_s=12.0):
+    """The CPU-baseline leg: every use of the FP64 oracle in the benchmark, all of it outside the
+    timed region. The oracle's volume update timed on the host cores on a bounded sample of the
+    step's workload (its rate is cpu_baseline), and the references the GPU results are checked
+    against: the oracle's volume at sampled reduced-volume points and, where affordable, its whole
+    greedy selection (else its first 60 selections; a stored full selection from the oracle is used
+    when present)."""
+    import numpy as np
+
+    import oracle
+
+    w, cs = m["w"], m["cs"]
+    radius, D, off = m["radius"], m["D"], m["off"]
+    o = oracle.get()
+    xc, al = m["xcn"], m["alpha"]
+    inside = np.flatnonzero(w.dwall < max(D))
+    per_point = np.zeros(w.n_v)
+    for l in range(len(radius)):
+        per_point += (w.dwall < D[l]) * (off[l + 1] - off[l])
+    rng = np.random.default_rng(5)
+    n_pick = int(min(inside.size, max(1000, 2e9 / max(1.0, per_point[inside].mean()))))
+    pick = np.sort(rng.choice(inside, n_pick, replace=False)) if n_pick < inside.size else inside
+    xv, dwp = np.ascontiguousarray(w.xv[:, pick]), np.ascontiguousarray(w.dwall[pick])
+    pairs = float(per_point[pick].sum())
+    omp = _omp()
+    cores = int(omp.omp_get_max_threads()) if omp else int(os.environ.get("OMP_NUM_THREADS", 1))
+
+    def timed(fn, budget):
+        reps, t = 0, 0.0
+        while t < budget and reps < 1000:
+            t0 = time.perf_counter()
+            fn()
+            t += time.perf_counter() - t0
+            reps += 1
+        return reps, t
+
+    vol = lambda pts=xv, d=dwp: o.volume(radius, D, off, xc, al, pts, d, basis=basis)
+    reps, t = timed(vol, budget_s)
+    cpu = {"value": pairs * reps / t, "unit": "evals/s", "cores": cores, "kind": "oracle",
+           "sample": f"volume update of the step's {cs.total} control points over {pick.size} of the "
+                     f"{inside.size} reduced-volume points ({pairs:.3g} pairs, every pair of points "
+                     f"within the support distances and controls of the same level, as the oracle "
+                     f"computes them), {reps} repetitions in {t:.1f} s"}
+    if omp:
+        sub = pick[: max(1, pick.size // max(1, cores))]
+        omp.omp_set_num_threads(1)
+        r1, t1 = timed(lambda: vol(np.ascontiguousarray(w.xv[:, sub]), np.ascontiguousarray(w.dwall[sub])), 2.0)
+        omp.omp_set_num_threads(cores)
+        cpu["single_thread_value"] = float(per_point[sub].sum()) * r1 / t1
+    # References for the parity checks.
+    ref_pick = np.random.default_rng(11).choice(inside, min(20000, inside.size), replace=False)
+    ref = {"pick": ref_pick,
+           "dv": o.volume(radius, D, off, xc, al, w.xv[:, ref_pick], w.dwall[ref_pick], basis=basis)}
+    got = cs.ctrl_idx[: cs.total].cpu().numpy()
+    gold = golden_selection(w) if basis == "c2" else None
+    if gold is not None:
+        ref["same"] = bool(np.array_equal(got, gold["ctrl_idx"]))
+        ref["check"] = (f"whole control set ({gold['ctrl_idx'].size} points) against the oracle's "
+                        f"stored full greedy selection (tests/golden, input hash {str(gold['input_sha'])})")
+        cpu["greedy_time_to_eps_s"] = float(gold["oracle_seconds"])
+        cpu["greedy_time_note"] = "oracle's whole greedy, timed where the stored selection was written"
+    elif big:
+        k = 60
+        r = o.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=k, seeds=w.seeds, basis=basis)
+        ref["same"] = bool(np.array_equal(got[:k], r.ctrl_idx[:k]))
+        ref["check"] = f"first {k} selections against the oracle's greedy capped at {k}"
+    else:
+        t0 = time.perf_counter()
+        r = o.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds,
+                     basis=basis)
+        cpu["greedy_time_to_eps_s"] = time.perf_counter() - t0
+        ref["same"] = bool(np.array_equal(got, r.ctrl_idx))
+        ref["check"] = "whole control set against the oracle's greedy"
+    return cpu, ref
+
+
+def precision_study(ctx, m, basis, ref):
+    """The FP32 pair form (shifted local origin, FP64 accumulation) beside the FP64 path on the
+    step's control sets: every level in FP32, and the guarded form a mixed-precision request runs
+    (FP32 only on the levels whose measured FP32 error at the surface is at most 1e-6 max |dS|),
+    against the FP64 GPU result and the FP64 oracle at sampled points."""
+    import torch
+
+    from paper_2107_13887_amd import rbfdef
+
+    w, cs, stream, vol_call, dv = m["w"], m["cs"], m["stream"], m["vol_call"], m["dv"]
     ms64 = _median_ms(stream, lambda: vol_call("fp64"), 10)
     vol_call("fp64")
     torch.cuda.synchronize()
@@ -417,60 +515,132 @@ def main():
     vol_call("mixed")
     torch.cuda.synchronize()
     dvmx = dv.cpu().numpy()
-    # The guarded form: FP32 only on the levels whose measured FP32 error at the surface is at
-    # most 1e-6 max |dS| (what a mixed-precision request runs). The step's greedy ran in FP64
-    # unless --precision mixed, so the measurement comes from one mixed greedy here.
-    csm = cs if args.precision == "mixed" else rbfdef.rbf_greedy_select(
-        ctx, xs, ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds, precision="mixed",
-        want_residual=False, basis=args.basis)
-    guard = ["mixed" if f else "fp64" for f in csm.fp32_levels()][: len(radius)]
+    csm = cs if m["precision"] == "mixed" else rbfdef.rbf_greedy_select(
+        ctx, m["xs"], m["ds"], w.radius, w.eps, rho=w.rho, cap=w.cap_total(), seeds=w.seeds,
+        precision="mixed", want_residual=False, basis=basis)
+    guard = ["mixed" if f else "fp64" for f in csm.fp32_levels()][: len(m["radius"])]
     msg = _median_ms(stream, lambda: vol_call(guard), 10)
     vol_call(guard)
     torch.cuda.synchronize()
     dvg = dv.cpu().numpy()
-    inside = np.flatnonzero(w.dwall < max(D))
-    pick = np.random.default_rng(11).choice(inside, min(20000, inside.size), replace=False)
-    xcn = cs.xc[:, : cs.total].cpu().numpy()
-    aln = cs.alpha[:, : cs.total].cpu().numpy()
-    orc = oracle.get()
-    ref_s = orc.volume(radius, D, off, xcn, aln, w.xv[:, pick], w.dwall[pick], basis=args.basis)
     study = {"fp64_volume_update_ms": ms64, "mixed_volume_update_ms": msmx,
              "mixed_speedup": ms64 / msmx,
              "mixed_vs_fp64_gpu": _normwise(dvmx, dv64),
-             "fp64_vs_oracle_sampled": _normwise(dv64[:, pick], ref_s),
-             "mixed_vs_oracle_sampled": _normwise(dvmx[:, pick], ref_s),
              "level_fp32_err_at_surface": csm.level_fp32_err[: csm.n_levels_used],
              "guarded_levels": guard,
              "guarded_volume_update_ms": msg,
-             "guarded_vs_fp64_gpu": _normwise(dvg, dv64),
-             "guarded_vs_oracle_sampled": _normwise(dvg[:, pick], ref_s),
-             "oracle_sample_points": int(pick.size)}
+             "guarded_speedup": ms64 / msg,
+             "guarded_vs_fp64_gpu": _normwise(dvg, dv64)}
+    if ref is not None:
+        pick = ref["pick"]
+        study.update({"fp64_vs_oracle_sampled": _normwise(dv64[:, pick], ref["dv"]),
+                      "mixed_vs_oracle_sampled": _normwise(dvmx[:, pick], ref["dv"]),
+                      "guarded_vs_oracle_sampled": _normwise(dvg[:, pick], ref["dv"]),
+                      "oracle_sample_points": int(pick.size)})
+    return study, dv64, dvg
 
-    # Selection parity outside the timed region: the whole greedy where the oracle affords it,
-    # otherwise its first 60 selections (the argmax sequence does not depend on the cap).
-    if big:
-        k = 60
-        ref = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=k, seeds=w.seeds,
-                         basis=args.basis)
-        same = bool(np.array_equal(cs.ctrl_idx[:k].cpu().numpy(), ref.ctrl_idx[:k]))
-        parity = f"first {k} selections against the oracle's greedy capped at {k}"
-    else:
-        ref = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
-                         seeds=w.seeds, basis=args.basis)
-        same = bool(np.array_equal(cs.ctrl_idx[: cs.total].cpu().numpy(), ref.ctrl_idx))
-        parity = "whole control set against the oracle's greedy"
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w, cs, radius, D, off, args.basis, big)
 
-    used = cs.n_levels_used
+def mesh_validity(w, dvs):
+    """Smallest corner Jacobian of the deformed O-H shell's hexahedra (positive: no cell inverted)
+    for each named volume displacement, beside the undeformed mesh's."""
+    import synth
+
+    meta = w.meta
+    args = (meta["n_chord"], meta["n_span"], meta["n_layers"])
+    out = {"undeformed": synth.hex_jacobian_range(w.xv, w.xs, *args)[0]}
+    for name, dv in dvs.items():
+        out[name] = synth.hex_jacobian_range(w.xv + dv, w.xs + w.ds, *args)[0]
+    return out
+
+
+def side_block(ctx, name, precision, basis, steps, warmup, with_oracle):
+    """A further workload of the same path: greedy and volume figures and the roofline fraction."""
+    m = run_workload(ctx, name, precision, basis, steps, warmup)
+    w, cs = m["w"], m["cs"]
+    big = w.n_s * w.cap_total() > 5e7
+    b = {"workload": f"{w.name}: {m['desc']}", "precision": precision,
+         "control_points_per_level": m["n_c"], "reduced_volume_points_per_level": m["n_d"],
+         "in_support_pairs_per_volume_update": m["in_support"],
+         "evaluated_pairs_per_volume_update": m["evaluated"],
+         "dense_pairs_per_volume_update": m["dense_pairs"],
+         "volume_update_ms": statistics.median(m["vol_ms"]),
+         "in_support_evals_per_s": m["in_support"] / (statistics.median(m["vol_ms"]) / 1e3),
+         "roofline": volume_roofline(m, precision, basis, name)}
+    b.update(greedy_block(m, basis))
+    ref = None
+    if with_oracle:
+        cpu, ref = oracle_leg(m, basis, big, budget_s=3.0)
+        b["cpu_baseline"] = cpu
+        b["selection_identical_to_oracle"] = ref["same"]
+        b["selection_check"] = ref["check"]
+    return m, b, ref
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2",
+                    help="cfg0..cfg3, sine2d, sine3d (one deformation per step), or cfg4 (serving mix)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--basis", default="c2", choices=["c0", "c2", "c4", "c6"])
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle leg (CPU baseline and the parity references)")
+    ap.add_argument("--extra-workloads", default="cfg1",
+                    help="comma-separated workloads measured after the main one (empty: none)")
+    ap.add_argument("--study-workload", default="cfg3",
+                    help="workload of the mixed-precision study with mesh validity (empty: none)")
+    ap.add_argument("--serve-geometries", type=int, default=16,
+                    help="geometries of the reduced serving mix replayed after the main timing (0: skip)")
+    ap.add_argument("--serve-scale", type=float, default=0.25,
+                    help="size scale of the reduced serving mix")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2107_13887_amd import rbfdef
+
+    if args.workload == "cfg4":
+        return serve_main(args)
+    ctx = rbfdef.rbf_ctx_create(0)
+    dev = torch.device("cuda:0")
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    m = run_workload(ctx, args.workload, args.precision, args.basis, args.steps, args.warmup)
+    w, cs, stream = m["w"], m["cs"], m["stream"]
+    big = w.n_s * w.cap_total() > 5e7       # the oracle's whole greedy would take minutes
+    radius, D, off = m["radius"], m["D"], m["off"]
+    # Secondary: the plain call on the caller's (unsorted) volume, with its per-call compaction.
+    plain_ms = _median_ms(stream, lambda: rbfdef.rbf_volume_update(
+        ctx, radius, D, off, cs.xc, cs.alpha, m["xv"], m["dw"], precision=args.precision,
+        basis=args.basis), 5)
+    cpu, ref = (None, None) if args.no_cpu_baseline else oracle_leg(m, args.basis, big)
+    study, _, _ = precision_study(ctx, m, args.basis, ref)
+
     # Dense FP64 solve (blocked Cholesky, trailing updates on FP64 MFMA): n^3/3 flops of the
     # factorization plus the dim triangular pairs, on the step's largest level and on the first
     # min(N_s, 4000) surface points with the widest radius (a dense SPD matrix).
+    used = cs.n_levels_used
     dense = []
+    n_c = m["n_c"]
     big_l = max(range(used), key=lambda l: n_c[l]) if used else 0
     sets = [("largest level of the step", cs.xc[:, off[big_l]:off[big_l + 1]].contiguous(),
-             ds[:, cs.ctrl_idx[off[big_l]:off[big_l + 1]]].contiguous(), radius[big_l])]
+             m["ds"][:, cs.ctrl_idx[off[big_l]:off[big_l + 1]]].contiguous(), radius[big_l])]
     nd = min(w.n_s, 4000)
-    sets.append((f"first {nd} surface points", xs[:, :nd].contiguous(), ds[:, :nd].contiguous(), w.radius[0]))
+    sets.append((f"first {nd} surface points", m["xs"][:, :nd].contiguous(), m["ds"][:, :nd].contiguous(),
+                 w.radius[0]))
     for label, sx, sd, rr in sets:
         nn = sx.shape[1]
         if nn < 2:
@@ -483,9 +653,10 @@ def main():
     # The greedy's per-iteration floor: one 64-point tile, every point selected (eps 0), so each
     # iteration is all synchronization and no streaming.
     n_tiny = min(64, w.n_s)
-    tiny = lambda: rbfdef.rbf_greedy_select(ctx, xs[:, :n_tiny].contiguous(), ds[:, :n_tiny].contiguous(),
-                                            [w.radius[0]], 0.0, rho=w.rho, cap=n_tiny, seeds=[[0]],
-                                            precision="fp64", want_residual=False, basis=args.basis)
+    xs_t, ds_t = m["xs"][:, :n_tiny].contiguous(), m["ds"][:, :n_tiny].contiguous()
+    tiny = lambda: rbfdef.rbf_greedy_select(ctx, xs_t, ds_t, [w.radius[0]], 0.0, rho=w.rho, cap=n_tiny,
+                                            seeds=[[0]], precision="fp64", want_residual=False,
+                                            basis=args.basis)
     tiny()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -493,64 +664,65 @@ def main():
     torch.cuda.synchronize()
     floor_us = (time.perf_counter() - t0) / max(ct.n_iterations, 1) * 1e6
 
-    # The greedy's Newton-basis stream (HBM-bound on large surfaces): an iteration with n finished
-    # columns reads the N_s x n basis and writes one column, and reads/writes E and reads x_s.
-    g_bytes = 0
-    for l in range(used):
-        m = n_c[l] if l < len(n_c) else 0
-        g_bytes += 8 * w.n_s * (m * (m - 1) // 2) + m * w.n_s * (9 + 24 * w.dim)
-    g_time = statistics.median(greedy_t)
+    vol_s = sum(m["vol_ms"]) / 1e3
     rec = {
         "metric": METRIC,
-        "value": value,
+        "value": m["in_support"] * args.steps / vol_s,
         "unit": "evals/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": m["wall"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{w.name}: {desc}", "precision": args.precision, "basis": args.basis,
+        "config": {"workload": f"{w.name}: {m['desc']}", "precision": args.precision, "basis": args.basis,
                    "control_points_per_level": n_c, "support_distance_per_level": D,
-                   "reduced_volume_points_per_level": n_d,
-                   "pairs_per_volume_update": pairs,
-                   "evaluated_pairs_per_volume_update": evaluated,
+                   "reduced_volume_points_per_level": m["n_d"],
+                   "in_support_pairs_per_volume_update": m["in_support"],
+                   "in_support_pairs_per_level": m["in_support_per_level"],
+                   "evaluated_pairs_per_volume_update": m["evaluated"],
+                   "dense_pairs_per_volume_update": m["dense_pairs"],
                    "parallelism": "single GPU"},
-        "greedy_time_to_eps_s": statistics.median(greedy_t),
-        "greedy_iterations": cs.n_iterations,
-        "greedy_iterations_per_s": cs.n_iterations / statistics.median(greedy_t),
-        "greedy_roofline": {"bound": "hbm", "achieved": g_bytes / g_time / 1e9, "peak": HBM_PEAK_GBS,
-                            "unit": "GB/s", "frac": g_bytes / g_time / 1e9 / HBM_PEAK_GBS,
-                            "algorithmic_bytes": g_bytes,
-                            "work_unit": "Newton-basis stream of every iteration (N_s x n read, one "
-                                         "column written, E and x_s), whole greedy call timed"},
+        "value_note": "in-support RBF evaluations (psi > 0 and phi > 0) per second of the volume update: "
+                      "in-support pairs per call x steps / the calls' device time (hipEvents on the launch "
+                      "stream); dense_evals_per_s counts every reduced point with every control of its level",
+        "dense_evals_per_s": m["dense_pairs"] * args.steps / vol_s,
+        "evaluated_evals_per_s": m["evaluated"] * args.steps / vol_s,
+        "volume_update_ms": statistics.median(m["vol_ms"]),
+        "plain_volume_update_ms": plain_ms,
         "greedy_iteration_floor_us": floor_us,
         "greedy_error_curve": error_curve(cs, w),
         "dense_solve": dense,
-        "greedy_levels": [{"controls": n_c[l] if l < len(n_c) else 0, "seconds": cs.level_seconds[l],
-                           "max_err_in": cs.level_in_max[l], "max_err_out": cs.level_max_err[l]}
-                          for l in range(used)],
-        "volume_update_ms": statistics.median(vol_ms),
-        "plain_volume_update_ms": plain_ms,
-        "plain_volume_update_evals_per_s": pairs / (plain_ms / 1e3),
-        "selection_identical_to_oracle": same,
-        "selection_check": parity,
+        "selection_identical_to_oracle": ref["same"] if ref else None,
+        "selection_check": ref["check"] if ref else None,
         "precision_study": study,
         "p50_latency_ms": None,
         "p99_latency_ms": None,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
-                     "frac": achieved / peak,
-                     "traffic": measured_traffic(args.workload, args.precision)
-                     if args.basis == "c2" else None,
-                     "kernel": kname, "kernel_avg_ms": avg_kernel_s * 1e3, "kernel_launches": k_n,
-                     "work_unit": "evaluated (point, control) pairs per launch, "
-                                  "controls whose support misses a point block skipped"},
+        "roofline": volume_roofline(m, args.precision, args.basis, args.workload),
         "cpu_baseline": cpu,
     }
-    rbfdef.rbf_geom_release(ctx, geom)
+    rec.update(greedy_block(m, args.basis))
+    rbfdef.rbf_geom_release(ctx, m["geom"])
+    del m
+    extras = {}
+    for name in [x for x in args.extra_workloads.split(",") if x and x != args.workload]:
+        me, b, _ = side_block(ctx, name, "fp64", args.basis, max(5, args.steps // 2), 2,
+                              not args.no_cpu_baseline)
+        rbfdef.rbf_geom_release(ctx, me["geom"])
+        extras[name] = b
+    if extras:
+        rec["other_workloads"] = extras
+    if args.study_workload:
+        ms_, b, ref_s = side_block(ctx, args.study_workload, "mixed", args.basis, 3, 1, not args.no_cpu_baseline)
+        st, dv64, dvg = precision_study(ctx, ms_, args.basis, ref_s)
+        b["precision_study"] = st
+        if ms_["w"].dim == 3 and "n_chord" in ms_["w"].meta:
+            b["min_hex_jacobian"] = mesh_validity(ms_["w"], {"fp64": dv64, "guarded_mixed": dvg})
+        rbfdef.rbf_geom_release(ctx, ms_["geom"])
+        rec["mixed_precision_workload"] = b
     if args.serve_geometries > 0:
         import synth
 

@@ -109,18 +109,36 @@ def layer_fractions(n_layers: int, first_layer: float, length: float) -> np.ndar
     return (q**j - 1.0) / (q**n_layers - 1.0)
 
 
+def blended_rays(px, py, nx, ny, fx, fy, g, bend: float = 0.05):
+    """Layer points of rays that leave the wall along its outward normal n and turn into the
+    direction e = (F - P) / L, L = |F - P|, of the straight line to their far-field point F: at the
+    layer fraction g the point is P + r (w n + (1 - w) e) with r = g L and w = 1 / (1 + r / bend).
+    The ray's tangent turns monotonically from n at the wall to e, so the cells next to the wall
+    are orthogonal to it rather than sheared (a straight ray to the far field runs within a few
+    degrees of the surface near the trailing edge), and far out each ray is the straight one
+    shifted by bend (n - e). Returns [len(g), n] arrays."""
+    dx, dy = fx - px, fy - py
+    L = np.hypot(dx, dy)
+    ex, ey = dx / L, dy / L
+    r = g[:, None] * L[None]
+    w = 1.0 / (1.0 + r / bend)
+    return (px[None] + r * (w * nx[None] + (1.0 - w) * ex[None]),
+            py[None] + r * (w * ny[None] + (1.0 - w) * ey[None]))
+
+
 def omesh_2d(xs: np.ndarray, ys: np.ndarray, n_layers: int, first_layer: float,
              r_far: float = 20.0, center=(0.5, 0.0)):
-    """2D O-mesh annulus: layer ``j`` of ray ``i`` is S_i + g_j (F_i - S_i), where F_i is the
-    point of the far-field circle at S_i's polar angle about ``center``. The wall layer itself
-    is not part of the volume. Returned layer-major: volume index = (j - 1) * n_rays + i."""
+    """2D O-mesh annulus: layer ``j`` of ray ``i`` lies at the fraction g_j of a ray from the
+    surface point S_i to F_i, the point of the far-field circle at S_i's polar angle about
+    ``center``, leaving the wall along its normal (``blended_rays``). The wall layer itself is not
+    part of the volume. Returned layer-major: volume index = (j - 1) * n_rays + i."""
     cx, cy = center
     theta = np.arctan2(ys - cy, xs - cx)
     fx = cx + r_far * np.cos(theta)
     fy = cy + r_far * np.sin(theta)
+    nx, ny = contour_normals(xs, ys)
     g = layer_fractions(n_layers, first_layer, r_far - 0.5 * CHORD)
-    xv = xs[None, :] + g[:, None] * (fx - xs)[None, :]
-    yv = ys[None, :] + g[:, None] * (fy - ys)[None, :]
+    xv, yv = blended_rays(xs, ys, nx, ny, fx, fy, g)
     return xv.reshape(-1), yv.reshape(-1)
 
 
@@ -167,48 +185,97 @@ def wing_normals(xyz: np.ndarray, n_chord: int, n_span: int) -> np.ndarray:
     return (n * sign[None]).reshape(3, -1)
 
 
-def oh_shell_3d(xyz: np.ndarray, n_chord: int, n_span: int, n_layers: int,
-                first_layer: float = 1e-3, r_far: float = 10.0):
-    """O-H shell volume: from each surface point, a ray in its section plane to the circle of
-    radius ``r_far`` about the local mid-chord, with the geometric layer law of ``omesh_2d``.
-    Layer-major: volume index = (j - 1) * n_s + k * n_chord + i."""
-    P = xyz.reshape(3, n_span, n_chord)
-    xmid = P[0].min(axis=1, keepdims=True) + 0.5 * CHORD
-    theta = np.arctan2(P[2], P[0] - xmid)
-    FX = xmid + r_far * np.cos(theta)
-    FZ = r_far * np.sin(theta)
+def c_grid_section(xc: np.ndarray, zc: np.ndarray, n_wake: int, n_layers: int,
+                   first_layer: float = 1e-3, r_far: float = 10.0):
+    """C-grid of one wing section in its own plane (abscissa from the leading edge, chord 1).
+
+    The C-line runs counter-clockwise: the upper side of the wake cut from its far end to the
+    trailing edge, the contour (trailing edge, upper surface, leading edge, lower surface), the
+    trailing edge again, then the lower side of the cut out to its far end. The cut holds
+    ``n_wake`` points on z = 0 from the trailing edge to x = 0.5 + r_far (geometric spacing that
+    starts from the contour's trailing-edge spacing); each appears on both sides of the C-line.
+    From every C-line node an off-body line of ``n_layers`` points leaves along the C-line normal
+    and bends into its far point (``blended_rays``): straight up or down for the cut, and for the
+    contour a point of the far boundary: straight above or below the node behind mid-chord, on
+    the half circle of radius r_far about mid-chord at the node's polar angle in front of it. The
+    trailing edge, the corner of an O-grid, is a kink of a few degrees of the C-line here, so no
+    cell there is a thin wedge.
+
+    Returns (cut_x [n_wake], line_x, line_z [n_layers, m]) with m = 2 n_wake + n + 1 C-line
+    nodes: layer j >= 1 of node p at line_x[j - 1, p], line_z[j - 1, p]."""
+    n = xc.size
+    x_te, x_far = xc[0], 0.5 * CHORD + r_far
+    h0 = math.hypot(xc[1] - xc[0], zc[1] - zc[0])
+    cut = x_te + (x_far - x_te) * layer_fractions(n_wake, h0, x_far - x_te)
+    px = np.concatenate([cut[::-1], [x_te], xc[1:], [x_te], cut])
+    pz = np.concatenate([np.zeros(n_wake), [zc[0]], zc[1:], [zc[0]], np.zeros(n_wake)])
+    m = px.size
+    tx = np.empty(m)
+    tz = np.empty(m)
+    tx[1:-1], tz[1:-1] = px[2:] - px[:-2], pz[2:] - pz[:-2]
+    tx[0], tz[0] = px[1] - px[0], pz[1] - pz[0]
+    tx[-1], tz[-1] = px[-1] - px[-2], pz[-1] - pz[-2]
+    norm = np.hypot(tx, tz)
+    nx, nz = tz / norm, -tx / norm
+    fx = px.copy()
+    fz = np.concatenate([np.full(n_wake, r_far), np.zeros(n + 1), np.full(n_wake, -r_far)])
+    # Contour nodes onto the far boundary: the rear half of the section (behind mid-chord)
+    # straight up or down onto z = +-r_far, the front half onto the half circle at the node's
+    # polar angle about mid-chord, so the order along the C-line is kept.
+    body = slice(n_wake, n_wake + n + 1)
+    th = np.arctan2(pz[body], px[body] - 0.5 * CHORD)
+    rear = px[body] >= 0.5 * CHORD
+    up = np.arange(n + 1) <= n // 2
+    bx = np.where(rear, px[body], 0.5 * CHORD + r_far * np.cos(th))
+    bz = np.where(rear, np.where(up, r_far, -r_far), r_far * np.sin(th))
+    fx[body], fz[body] = bx, bz
     g = layer_fractions(n_layers, first_layer, r_far - 0.5 * CHORD)
-    X = P[0][None] + g[:, None, None] * (FX - P[0])[None]
-    Y = np.broadcast_to(P[1][None], X.shape)
-    Z = P[2][None] + g[:, None, None] * (FZ - P[2])[None]
-    return np.stack([X.reshape(-1), np.ascontiguousarray(Y).reshape(-1), Z.reshape(-1)])
+    lx, lz = blended_rays(px, pz, nx, nz, fx, fz, g)
+    return cut, lx, lz
 
 
-def hex_jacobian_range(vol: np.ndarray, surf: np.ndarray, n_chord: int, n_span: int, n_layers: int):
-    """(min, max) of the corner Jacobian (triple product of the three edges at the first corner)
-    over the hexahedra of an O-H shell whose layer 0 is the surface. A valid mesh has every cell
-    of one sign, the sign of the undeformed mesh (a mesh-validity post-check)."""
-    full = np.concatenate([surf.reshape(3, 1, n_span, n_chord),
-                           vol.reshape(3, n_layers, n_span, n_chord)], axis=1)
-    ip = np.roll(np.arange(n_chord), -1)
-    a = full[:, :-1, :-1, :]
-    ei = full[:, :-1, :-1, ip] - a
-    ek = full[:, :-1, 1:, :] - a
-    ej = full[:, 1:, :-1, :] - a
-    jac = np.einsum("cljk,cljk->ljk", ej, np.cross(ei, ek, axis=0))
-    return float(jac.min()), float(jac.max())
+def ch_shell_3d(xc: np.ndarray, zc: np.ndarray, xle: np.ndarray, yk: np.ndarray, n_wake: int,
+                n_layers: int, first_layer: float = 1e-3, r_far: float = 10.0):
+    """C-H shell around the swept wing: the section C-grid (``c_grid_section``) at every span
+    station, shifted to the station's leading edge. Volume order: the cut points of every station
+    (station-major), then layer by layer the off-body points of every station and C-line node:
+    index n_wake n_span + (j - 1) m n_span + k m + p for layer j >= 1, station k, node p."""
+    cut, lx, lz = c_grid_section(xc, zc, n_wake, n_layers, first_layer, r_far)
+    n_span, m = yk.size, lx.shape[1]
+    X0 = (xle[:, None] + cut[None, :]).reshape(-1)
+    Y0 = np.repeat(yk, n_wake)
+    Z0 = np.zeros(X0.size)
+    X = (xle[None, :, None] + lx[:, None, :]).reshape(-1)
+    Y = np.broadcast_to(yk[None, :, None], (n_layers, n_span, m)).reshape(-1)
+    Z = np.broadcast_to(lz[:, None, :], (n_layers, n_span, m)).reshape(-1)
+    return np.stack([np.concatenate([X0, X]), np.concatenate([Y0, Y]), np.concatenate([Z0, Z])])
 
 
-def hex_jacobians(vol: np.ndarray, surf: np.ndarray, n_chord: int, n_span: int, n_layers: int):
-    """Corner Jacobian of every hexahedron of the O-H shell, shape [n_layers, n_span - 1, n_chord]
-    (layer, span station, chord index)."""
-    full = np.concatenate([surf.reshape(3, 1, n_span, n_chord),
-                           vol.reshape(3, n_layers, n_span, n_chord)], axis=1)
-    ip = np.roll(np.arange(n_chord), -1)
-    a = full[:, :-1, :-1, :]
-    ei = full[:, :-1, :-1, ip] - a
-    ek = full[:, :-1, 1:, :] - a
-    ej = full[:, 1:, :-1, :] - a
+def ch_nodes(vol: np.ndarray, surf: np.ndarray, n_chord: int, n_span: int, n_layers: int, n_wake: int):
+    """Node coordinates of the C-H shell as a [3, n_layers + 1, n_span, m] grid (layer 0 on the
+    C-line: cut points and surface points, the trailing edge at both of its C-line places)."""
+    m = 2 * n_wake + n_chord + 1
+    S = surf.reshape(3, n_span, n_chord)
+    cut = vol[:, : n_wake * n_span].reshape(3, n_span, n_wake)
+    G = np.empty((3, n_layers + 1, n_span, m))
+    G[:, 0, :, :n_wake] = cut[:, :, ::-1]
+    G[:, 0, :, n_wake] = S[:, :, 0]
+    G[:, 0, :, n_wake + 1: n_wake + n_chord] = S[:, :, 1:]
+    G[:, 0, :, n_wake + n_chord] = S[:, :, 0]
+    G[:, 0, :, n_wake + n_chord + 1:] = cut
+    G[:, 1:] = vol[:, n_wake * n_span:].reshape(3, n_layers, n_span, m)
+    return G
+
+
+def hex_jacobians(vol: np.ndarray, surf: np.ndarray, meta: dict) -> np.ndarray:
+    """Corner Jacobian (triple product of the three edges at the first corner) of every
+    hexahedron of the C-H shell, shape [n_layers, n_span - 1, m - 1] (layer, span station, C-line
+    segment). A valid mesh has every cell of one sign, the sign of the undeformed mesh."""
+    G = ch_nodes(vol, surf, meta["n_chord"], meta["n_span"], meta["n_layers"], meta["n_wake"])
+    a = G[:, :-1, :-1, :-1]
+    ei = G[:, :-1, :-1, 1:] - a
+    ek = G[:, :-1, 1:, :-1] - a
+    ej = G[:, 1:, :-1, :-1] - a
     return np.einsum("cljk,cljk->ljk", ej, np.cross(ei, ek, axis=0))
 
 
@@ -319,19 +386,25 @@ def workload_cfg1(n_s: int = 4000, n_layers: int = 100, precision: str = "fp64")
                     precision=precision, meta=dict(cfg=1, n_layers=n_layers))
 
 
-def wing_3d(n_chord: int, n_span: int, n_layers: int):
+def wing_3d(n_chord: int, n_span: int, n_layers: int, n_wake: int):
+    """Swept-wing surface and its C-H shell: (xyz, volume, section x, section z, span stations)."""
     xyz, xc, zc, yk = wing_surface(n_chord, n_span)
-    vol = oh_shell_3d(xyz, n_chord, n_span, n_layers)
+    xle = yk * math.tan(math.radians(25.0))
+    vol = ch_shell_3d(xc, zc, xle, yk, n_wake, n_layers)
     return xyz, vol, xc, zc, yk
 
 
-def workload_cfg2(n_chord: int = 400, n_span: int = 200, n_layers: int = 50,
+def wing_meta(n_chord: int, n_span: int, n_layers: int, n_wake: int, **kw) -> dict:
+    return dict(n_chord=n_chord, n_span=n_span, n_layers=n_layers, n_wake=n_wake, **kw)
+
+
+def workload_cfg2(n_chord: int = 400, n_span: int = 200, n_layers: int = 40, n_wake: int = 49,
                   precision: str = "fp64", cap: int = 4000) -> Workload:
     """3D iced wing: leading-edge horn (the 2D horn profile in local arc length) whose amplitude
     is 0.04c (1 - 0.5 y/b)(1 + 0.1 u_k), u_k ~ U[-1, 1] per station. Levels R = 3c, 0.8c, 0.2c,
     eps = 1e-4c, at most ``cap`` control points in total, D = 1c."""
     rng = np.random.default_rng(SEED_BASE + 2)
-    xyz, vol, xc, zc, yk = wing_3d(n_chord, n_span, n_layers)
+    xyz, vol, xc, zc, yk = wing_3d(n_chord, n_span, n_layers, n_wake)
     n = wing_normals(xyz, n_chord, n_span)
     s = arc_length_from_te(xc, zc)
     s0 = upper_arc_length_at(xc, s, 0.01)
@@ -342,8 +415,7 @@ def workload_cfg2(n_chord: int = 400, n_span: int = 200, n_layers: int = 50,
     ds = n * amp[None, :]
     return Workload("cfg2_swept_wing_3d_ice", 3, xyz, ds, vol, wall_distance(xyz, vol),
                     radius=[3.0, 0.8, 0.2], eps=1e-4, D=1.0, seeds=[[0]], cap=cap,
-                    precision=precision,
-                    meta=dict(cfg=2, n_chord=n_chord, n_span=n_span, n_layers=n_layers))
+                    precision=precision, meta=wing_meta(n_chord, n_span, n_layers, n_wake, cfg=2))
 
 
 def bend_twist(xyz: np.ndarray, semi_span: float, tip_deflection: float = 0.1,
@@ -361,15 +433,15 @@ def bend_twist(xyz: np.ndarray, semi_span: float, tip_deflection: float = 0.1,
     return np.stack([xr - X, np.zeros_like(Y), zr - Z + dz])
 
 
-def workload_cfg3(n_chord: int = 400, n_span: int = 200, n_layers: int = 50, cap: int = 4000) -> Workload:
+def workload_cfg3(n_chord: int = 400, n_span: int = 200, n_layers: int = 40, n_wake: int = 49,
+                  cap: int = 4000) -> Workload:
     """3D global deformation: the wing and meshes of the iced-wing case deformed by parabolic
     bending (tip deflection 0.1b) plus linear twist (5 degrees at the tip). Mixed precision."""
-    xyz, vol, xc, zc, yk = wing_3d(n_chord, n_span, n_layers)
+    xyz, vol, xc, zc, yk = wing_3d(n_chord, n_span, n_layers, n_wake)
     ds = bend_twist(xyz, yk[-1])
     return Workload("cfg3_swept_wing_3d_bend_twist", 3, xyz, ds, vol, wall_distance(xyz, vol),
                     radius=[3.0, 0.8, 0.2], eps=1e-4, D=1.0, seeds=[[0]], cap=cap,
-                    precision="mixed",
-                    meta=dict(cfg=3, n_chord=n_chord, n_span=n_span, n_layers=n_layers))
+                    precision="mixed", meta=wing_meta(n_chord, n_span, n_layers, n_wake, cfg=3))
 
 
 def workload_sine2d(n_s: int = 4000, n_layers: int = 100) -> Workload:
@@ -386,16 +458,17 @@ def workload_sine2d(n_s: int = 4000, n_layers: int = 100) -> Workload:
                     meta=dict(n_layers=n_layers))
 
 
-def workload_sine3d(n_chord: int = 400, n_span: int = 200, n_layers: int = 50, cap: int = 4000) -> Workload:
+def workload_sine3d(n_chord: int = 400, n_span: int = 200, n_layers: int = 40, n_wake: int = 49,
+                    cap: int = 4000) -> Workload:
     """The paper's global-deformation benchmark on the swept wing (eq. (27)): the displacement
     normal to the wing plane is 0.03 sin(4 pi s) with s the spanwise coordinate in units of c (the
     paper's y and z are this generator's z and y). R = 3c on four levels, reduction 0.1 per level,
     eps = 1e-4c, at most ``cap`` control points, k = 5. Mesh as the iced-wing case."""
-    xyz, vol, xc, zc, yk = wing_3d(n_chord, n_span, n_layers)
+    xyz, vol, xc, zc, yk = wing_3d(n_chord, n_span, n_layers, n_wake)
     ds = np.stack([np.zeros(xyz.shape[1]), np.zeros(xyz.shape[1]), 0.03 * np.sin(4.0 * np.pi * xyz[1])])
     return Workload("sine3d_swept_wing", 3, xyz, ds, vol, wall_distance(xyz, vol), radius=[3.0] * 4,
                     eps=1e-4, D=1.0, seeds=[[0]], cap=cap, d_factor=5.0,
-                    meta=dict(n_chord=n_chord, n_span=n_span, n_layers=n_layers))
+                    meta=wing_meta(n_chord, n_span, n_layers, n_wake))
 
 
 def workload(cfg: int, **kw) -> Workload:
@@ -485,8 +558,8 @@ def serving_mix(n_geom: int = 64, steps: int = 4, rate: float = 20.0, frac_2d: f
         else:
             n_c = max(40, int(400 * scale) - int(400 * scale) % 2)
             n_span = max(6, int(rng.integers(25, 201) * scale))
-            n_r = max(4, int(50 * min(1.0, scale * 4)))
-            xyz, vol, xc2, zc2, yk = wing_3d(n_c, n_span, n_r)
+            n_r = max(4, int(40 * min(1.0, scale * 4)))
+            xyz, vol, xc2, zc2, yk = wing_3d(n_c, n_span, n_r, max(4, n_c // 8 - 1))
             n = wing_normals(xyz, n_c, n_span)
             if rng.uniform() < 0.5:
                 s = arc_length_from_te(xc2, zc2)

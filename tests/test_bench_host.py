@@ -40,10 +40,13 @@ def test_committed_traffic_matches_current_kernel(workload, precision):
 
 
 def test_traffic_dropped_for_another_kernel_source(tmp_path, monkeypatch):
-    """A change to the code of the kernel-sum source (not to its comments) drops the traffic."""
+    """A change to the code of the kernel-sum device sources (not to their comments) drops the
+    traffic."""
     csrc = tmp_path / "paper_2107_13887_amd" / "csrc"
     csrc.mkdir(parents=True)
     shutil.copytree(os.path.join(ROOT, "profiles"), tmp_path / "profiles")
+    for name in bench.KERNEL_SOURCES:
+        shutil.copy(os.path.join(ROOT, "paper_2107_13887_amd", "csrc", name), csrc / name)
     src = open(os.path.join(ROOT, "paper_2107_13887_amd", "csrc", "ksum.hip")).read()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
 
@@ -60,3 +63,29 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stdout
+
+
+def test_in_support_pair_count_is_exact():
+    """The headline's work count: pairs of a reduced volume point (d < D_l) and a control of the
+    same level within its support radius (||x - x_c|| < R_l), equal to a brute-force count."""
+    import numpy as np
+
+    import synth
+
+    w = synth.random_workload(3, 3, 200, 5000, [1.0, 0.4], 1e-6)
+    rng = np.random.default_rng(0)
+    xc = rng.uniform(-1, 1, (3, 50))
+    off, R, D = [0, 20, 50], [1.0, 0.4], [1.2, 0.8]
+    total, per = bench.in_support_pairs(w, R, D, off, xc)
+    want = []
+    for l in range(2):
+        pts = w.xv[:, w.dwall < D[l]]
+        d = np.sqrt(((pts[:, :, None] - xc[:, None, off[l]:off[l + 1]]) ** 2).sum(0))
+        want.append(int((d < R[l]).sum()))
+    assert per == want and total == sum(want)
+    # a control exactly one radius away from a point is outside the support (phi = 0 there)
+    w.xv[:, 0] = xc[:, 0] + np.array([R[0], 0.0, 0.0])
+    w.dwall[0] = 0.0
+    pts = w.xv[:, w.dwall < D[0]]
+    d = np.sqrt(((pts[:, :, None] - xc[:, None, :20]) ** 2).sum(0))
+    assert bench.in_support_pairs(w, R, D, off, xc)[1][0] == int((d < R[0]).sum())
