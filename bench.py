@@ -61,21 +61,22 @@ def build_workload(name):
     if name == "cfg0":
         return synth.workload_cfg0(), "2D NACA0012 single level: N_s=400, N_v=20000, R=2c, eps=1e-5c, D=1c"
     if name == "cfg2":
-        return synth.workload_cfg2(), ("3D swept wing ice horn: N_s=80000, N_v=4000000, R_l=3c/0.8c/0.2c, "
-                                       "eps=1e-4c, cap 4000, D=1c")
+        return synth.workload_cfg2(), ("3D swept wing ice horn: N_s=80000, N_v=4001800 (C-H shell), "
+                                       "R_l=3c/0.8c/0.2c, eps=1e-4c, cap 4000, D=1c")
     if name == "cfg4":
         return None, ("serving mix: 64 geometries (60% 2D airfoils, N_s 500-8000; 40% 3D wings, "
                       "N_s 10k-80k), 4 warm-started icing steps each, Poisson arrivals at 20/s, "
                       "eps in {1e-4, 1e-5}, mixed precision")
     if name == "cfg3":
-        return synth.workload_cfg3(), ("3D swept wing bend+twist: N_s=80000, N_v=4000000, "
+        return synth.workload_cfg3(), ("3D swept wing bend+twist: N_s=80000, N_v=4001800 (C-H shell), "
                                        "R_l=3c/0.8c/0.2c, eps=1e-4c, cap 4000, D=1c")
     if name == "sine2d":
         return synth.workload_sine2d(), ("2D NACA0012 global deformation dy = 0.01 sin(15 pi x): N_s=4000, "
                                          "N_v=400000, R=2c on 5 levels, eps=1e-5 max|dS|, D_l = 5 max|dS_l|")
     if name == "sine3d":
         return synth.workload_sine3d(), ("3D swept wing global deformation 0.03 sin(4 pi y): N_s=80000, "
-                                         "N_v=4000000, R=3c on 4 levels, eps=1e-4c, cap 4000, D_l = 5 max|dS_l|")
+                                         "N_v=4001800 (C-H shell), R=3c on 4 levels, eps=1e-4c, cap 4000, "
+                                         "D_l = 5 max|dS_l|")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -541,15 +542,20 @@ def precision_study(ctx, m, basis, ref):
 
 
 def mesh_validity(w, dvs):
-    """Smallest corner Jacobian of the deformed O-H shell's hexahedra (positive: no cell inverted)
-    for each named volume displacement, beside the undeformed mesh's."""
+    """Smallest corner Jacobian of the deformed C-H shell's hexahedra, each oriented by the sign of
+    the undeformed cell (positive: no cell inverted), for each named volume displacement (the
+    surface moved by its prescribed displacement), with the undeformed mesh's smallest."""
+    import numpy as np
+
     import synth
 
-    meta = w.meta
-    args = (meta["n_chord"], meta["n_span"], meta["n_layers"])
-    out = {"undeformed": synth.hex_jacobian_range(w.xv, w.xs, *args)[0]}
+    j0 = synth.hex_jacobians(w.xv, w.xs, w.meta)
+    s0 = np.sign(j0)
+    out = {"undeformed": float(np.abs(j0).min()), "cells": int(j0.size)}
     for name, dv in dvs.items():
-        out[name] = synth.hex_jacobian_range(w.xv + dv, w.xs + w.ds, *args)[0]
+        j = synth.hex_jacobians(w.xv + dv, w.xs + w.ds, w.meta) * s0
+        out[name] = float(j.min())
+        out[name + "_inverted_cells"] = int((j <= 0).sum())
     return out
 
 

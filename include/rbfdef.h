@@ -48,7 +48,11 @@ typedef int32_t rbf_status;
                         accumulator; greedy factor, convergence check and residuals stay FP64.
                         The greedy measures each level's FP32 error at the surface
                         (level_fp32_err), and a request runs a level's volume sums in FP32 only
-                        when that error is at most RBF_MIXED_TOL max_i ||dS_i|| (FP64 otherwise) */
+                        when that error is at most RBF_MIXED_TOL max_i ||dS_i|| (FP64 otherwise):
+                        that guarded form is held to 1e-5 of the result's scale. A direct call with
+                        RBF_MIXED on every level does not meet that on cancelling sums (the FP32
+                        pair error grows with sum |phi alpha|, e.g. ice shapes with large weights):
+                        there only the FP32 rounding of the summed terms bounds its error */
 #define RBF_MIXED_TOL 1e-6
 
 /* Basis functions phi(eta), eta = ||r - r_c|| / R, the Wendland functions of Table 1, each zero

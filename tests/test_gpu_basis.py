@@ -10,25 +10,12 @@ import pytest
 import torch
 
 import synth
-from helpers import fp64_bound, mixed_bound, to_dev
+from helpers import fp64_bound, mixed_bound, sum_magnitude, to_dev
 from paper_2107_13887_amd import rbfdef
 
 pytestmark = pytest.mark.gpu
 
 BASES = ["c0", "c2", "c4", "c6"]
-
-
-def _S(orc, radius, level_off, xc, alpha, pts, dwall, D, basis):
-    """max_p sum_l psi sum_c |phi alpha| with the given basis (rounding scale of the sums)."""
-    out = np.zeros(pts.shape[1])
-    for l in range(len(radius)):
-        a, b = int(level_off[l]), int(level_off[l + 1])
-        if b == a:
-            continue
-        s = orc.evaluate(radius[l], xc[:, a:b], np.abs(alpha[:, a:b]), pts, basis=basis)
-        w = np.maximum(0.0, 1.0 - dwall / D[l]) if dwall is not None else 1.0
-        out += w * np.abs(s).sum(0)
-    return out.max()
 
 
 @pytest.mark.parametrize("basis", BASES)
@@ -46,7 +33,7 @@ def test_basis_greedy_and_volume(gctx, orc, basis, dim):
     xc = np.ascontiguousarray(w.xs[:, ref.ctrl_idx])
     want = orc.volume(w.radius, D, ref.level_off, xc, ref.alpha, w.xv, w.dwall, basis=basis)
     scale = np.sqrt((want ** 2).sum(0)).max()
-    S = _S(orc, w.radius, ref.level_off, xc, ref.alpha, w.xv, w.dwall, D, basis)
+    S = sum_magnitude(orc, w.radius, ref.level_off, xc, ref.alpha, w.xv, w.dwall, D, basis)
     for precision, bound in (("fp64", fp64_bound), ("mixed", mixed_bound)):
         dv = rbfdef.rbf_volume_update(gctx, w.radius, D, list(ref.level_off), to_dev(xc), to_dev(ref.alpha),
                                       to_dev(w.xv), to_dev(w.dwall), precision=precision, basis=basis)
@@ -81,7 +68,7 @@ def test_basis_solve_and_evaluate(gctx, orc, basis):
     want = orc.evaluate(1.1, xc, ref, pts, basis=basis)
     out = rbfdef.rbf_evaluate(gctx, 1.1, to_dev(xc), to_dev(ref), to_dev(pts), basis=basis)
     torch.cuda.synchronize()
-    S = _S(orc, [1.1], [0, 300], xc, ref, pts, None, None, basis)
+    S = sum_magnitude(orc, [1.1], [0, 300], xc, ref, pts, None, None, basis)
     scale = np.sqrt((want ** 2).sum(0)).max()
     assert np.sqrt(((out.cpu().numpy() - want) ** 2).sum(0)).max() <= fp64_bound(scale, S)
 

@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import synth
-from helpers import fp64_bound, sum_magnitude, to_dev
+from helpers import check_fp64, fp64_bound, sum_magnitude, to_dev
 from paper_2107_13887_amd import rbfdef
 
 pytestmark = pytest.mark.gpu
@@ -61,7 +61,7 @@ def test_culled_resident_volume(gctx, orc, dim, n_s, n_v, radius, D):
     S = sum_magnitude(orc, w.radius, res.level_off, xc, res.alpha, w.xv, w.dwall, D)
     err = np.sqrt(((got - ref) ** 2).sum(0)).max()
     print(f"error {err:.3e} (bound {fp64_bound(scale, S):.3e})")
-    assert err <= fp64_bound(scale, S)
+    check_fp64(err, scale, S)
     far = w.dwall >= max(D)
     assert np.all(got[:, far] == 0.0) and not np.any(np.signbit(got[:, far]))
     # evaluated pairs: at least every in-support pair, at most every pair of every stored block
@@ -99,7 +99,7 @@ def test_culling_takes_effect(gctx, orc):
     scale = np.sqrt((ref ** 2).sum(0)).max()
     S = sum_magnitude(orc, w.radius, res.level_off, xc, res.alpha, w.xv, w.dwall, D)
     err = np.sqrt(((dv.cpu().numpy() - ref) ** 2).sum(0)).max()
-    assert err <= fp64_bound(scale, S)
+    check_fp64(err, scale, S)
     rbfdef.rbf_geom_release(gctx, geom)
 
 

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 import synth
-from helpers import fp64_bound, normwise, sum_magnitude, to_dev
+from helpers import check_fp64, fp64_bound, normwise, sum_magnitude, to_dev
 from paper_2107_13887_amd import rbfdef
 
 pytestmark = pytest.mark.gpu
@@ -88,7 +88,7 @@ def test_greedy_cfg1_full_and_volume(gctx, orc):
     S = sum_magnitude(orc, w.radius, ref.level_off, xc, ref.alpha, w.xv, w.dwall, D)
     err = np.sqrt(((dv.cpu().numpy() - ref_dv) ** 2).sum(0)).max()
     print(f"volume error {err:.3e} = {err / scale:.3e} normwise (bound {fp64_bound(scale, S):.3e})")
-    assert err <= fp64_bound(scale, S)
+    check_fp64(err, scale, S)
 
 
 def test_greedy_all_selected_and_cap(gctx, orc):

@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import synth
-from helpers import fp64_bound, normwise, sum_magnitude, to_dev
+from helpers import check_fp64, fp64_bound, normwise, sum_magnitude, to_dev
 from paper_2107_13887_amd import rbfdef
 
 pytestmark = pytest.mark.gpu
@@ -56,7 +56,7 @@ def test_resident_volume_matches_plain_path(gctx, orc):
     got = dv.cpu().numpy()
     err = np.sqrt(((got - ref_dv) ** 2).sum(0)).max()
     print(f"resident volume error {err:.3e} (bound {fp64_bound(scale, S):.3e})")
-    assert err <= fp64_bound(scale, S)
+    check_fp64(err, scale, S)
     assert np.all(got[:, w.dwall >= w.D] == 0.0)
     rbfdef.rbf_geom_release(gctx, geom)
 
@@ -80,7 +80,7 @@ def test_device_wall_distance(gctx, orc):
     scale = np.sqrt((ref ** 2).sum(0)).max()
     err = np.sqrt(((d2.cpu().numpy() - ref) ** 2).sum(0)).max()
     print(f"device wall distance: difference {err:.3e} (bound {fp64_bound(scale, S):.3e})")
-    assert err <= fp64_bound(scale, S)
+    check_fp64(err, scale, S)
     rbfdef.rbf_geom_release(gctx, g1)
     rbfdef.rbf_geom_release(gctx, g2)
 
@@ -188,7 +188,7 @@ def test_geom_volume_update_matches_oracle(gctx, orc):
     scale = np.sqrt((want ** 2).sum(0)).max()
     S = sum_magnitude(orc, w.radius, ref.level_off, xc, ref.alpha, w.xv, w.dwall, D)
     err = np.sqrt(((got - want) ** 2).sum(0)).max()
-    assert err <= fp64_bound(scale, S)
+    check_fp64(err, scale, S)
     far = w.dwall >= max(D)
     assert np.all(got[:, far] == 0.0) and not np.any(np.signbit(got[:, far]))
     rbfdef.rbf_geom_release(gctx, geom)
@@ -253,7 +253,7 @@ def test_adaptive_support_distance(gctx, orc):
     err = np.sqrt(((got - want) ** 2).sum(0)).max()
     print(f"adaptive-D volume error {err:.3e} (bound {fp64_bound(scale, S):.3e}); "
           f"points per level {[int((w.dwall < d).sum()) for d in D]} of {w.n_v}")
-    assert err <= fp64_bound(scale, S)
+    check_fp64(err, scale, S)
     far = w.dwall >= max(D)
     assert np.all(got[:, far] == 0.0) and not np.any(np.signbit(got[:, far]))
     rbfdef.rbf_geom_release(gctx, geom)

@@ -13,7 +13,7 @@ import torch
 
 import oracle as oracle_mod
 import synth
-from helpers import fp64_bound, sum_magnitude, to_dev
+from helpers import check_fp64, fp64_bound, sum_magnitude, to_dev
 from paper_2107_13887_amd import rbfdef
 
 pytestmark = pytest.mark.gpu
@@ -53,7 +53,7 @@ def _run(gctx, orc, w, sample=None):
                       w.dwall[pick], D)
     err = np.sqrt(((got[:, pick] - want) ** 2).sum(0)).max()
     print(f"volume error {err:.3e} (bound {fp64_bound(scale, S):.3e}); D {['%.3g' % d for d in D]}")
-    assert err <= fp64_bound(scale, S)
+    check_fp64(err, scale, S)
 
 
 def test_sine_airfoil_reduced(gctx, orc):
