@@ -20,7 +20,8 @@
  *   - "stream" is a hipStream_t passed as void* (NULL = the default stream). Calls marked
  *     "blocking" return after their device work has finished; the others only enqueue it.
  *   - All device memory the library needs besides the caller's buffers comes from the context
- *     and counts against its HBM budget; RBF_E_NOMEM is returned when it would be exceeded.
+ *     and counts against its HBM budget; RBF_E_NOMEM is returned when it would be exceeded. The
+ *     one exception is the fixed scratch array of rbf_volume_update_noalloc.
  *   - Calls on one context are not thread-safe except rbf_submit, rbf_poll and rbf_wait.
  */
 #ifndef RBFDEF_H
@@ -183,6 +184,26 @@ rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const d
                              const double *xc, const double *alpha, int64_t n_v, const double *xv,
                              const double *dwall, double *dv, int32_t precision,
                              const int32_t *level_precision, int32_t basis, void *stream);
+
+/* Allocation-free form of rbf_volume_update, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, results and precision rules; it calls no hipMalloc or hipFree and no allocating
+ * library routine, records no timer events and counts no pairs. Its scratch (the reduced-point
+ * list, per-block counts and the partial sums of split control lists) is a fixed array of
+ * RBF_NOALLOC_SCRATCH_BYTES in the library's device memory, one per GPU, held until the process
+ * ends (its address is looked up once per device by rbf_ctx_create). n_v above
+ * RBF_NOALLOC_MAX_POINTS returns RBF_E_INVALID before any device work; when split partial sums
+ * would not fit, the control lists are split fewer times. Every call on one GPU uses that GPU's
+ * array and leaves its contents behind: calls that overlap on one GPU (other streams or threads)
+ * race and must be serialised by the caller. Enqueued on `stream`. */
+#define RBF_NOALLOC_SCRATCH_BYTES (64ull << 20)
+#define RBF_NOALLOC_MAX_POINTS 16000000
+rbf_status rbf_volume_update_noalloc(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
+                                     const double *D, const int32_t *level_off, int64_t ld_ctrl,
+                                     const double *xc, const double *alpha, int64_t n_v,
+                                     const double *xv, const double *dwall, double *dv,
+                                     int32_t precision, const int32_t *level_precision, int32_t basis,
+                                     void *stream);
 
 /* Interpolant evaluation, eq. (1) with the support of eq. (2), at n_p points:
  *   out_k(p) = base_k(p) - sign * sum_c phi(||x_p - xc_c|| / radius) alpha_k,c

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "librbfdef.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["ksum.hip", "ksum_host.cpp", "greedy.hip", "chol.hip", "capi.cpp", "serve.cpp"]
+SOURCES = ["ksum.hip", "ksum_host.cpp", "greedy.hip", "chol.hip", "capi.cpp", "serve.cpp", "noalloc.hip"]
 
 # Packed FP32 instructions are disabled on purpose: the FP32 path must not be silently rewritten
 # into v_pk_* forms.

@@ -244,6 +244,20 @@ rbf_status check_precision(int32_t precision, const int32_t *level_precision, in
     return RBF_OK;
 }
 
+// Device address of the fixed scratch array, looked up once per device (with that device
+// current) and kept for the process: each device holds its own copy of the array.
+static rbf_status scratch_for_device(int device, void **ptr)
+{
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;                    // trivially destructible, as is the table
+    static void *addr[MAX_DEVICES] = {};
+    if (device < 0 || device >= MAX_DEVICES) return fail(RBF_E_INVALID, "device %d out of range", device);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) RBF_TRY(noalloc_scratch_address(&addr[device]));
+    *ptr = addr[device];
+    return RBF_OK;
+}
+
 rbf_status validate_params(const rbf_greedy_params &p, int64_t n_s)
 {
     if (p.dim != 2 && p.dim != 3) return fail(RBF_E_INVALID, "dim must be 2 or 3 (got %d)", p.dim);
@@ -323,6 +337,7 @@ rbf_status rbf_ctx_create(int32_t device, uint64_t budget, rbf_ctx *out)
         budget = (uint64_t)(0.9 * (double)fr);
     }
     ctx->pool = std::make_unique<Pool>(device, budget);
+    RBF_TRY(scratch_for_device(device, &ctx->noalloc_scratch));
     *out = ctx.release();
     return RBF_OK;
 }
@@ -433,11 +448,12 @@ static rbf_status check_levels(int32_t n_levels, const double *radius, const dou
     return RBF_OK;
 }
 
-rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
-                             const double *D, const int32_t *level_off, int64_t ld_ctrl,
-                             const double *xc, const double *alpha, int64_t n_v, const double *xv,
-                             const double *dwall, double *dv, int32_t precision,
-                             const int32_t *level_precision, int32_t basis, void *stream)
+// Validated problem of a plain volume update (shared by the pool and the allocation-free forms).
+static rbf_status volume_problem(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
+                                 const double *D, const int32_t *level_off, int64_t ld_ctrl,
+                                 const double *xc, const double *alpha, int64_t n_v, const double *xv,
+                                 const double *dwall, double *dv, int32_t precision,
+                                 const int32_t *level_precision, int32_t basis, SumProblem &pb)
 {
     if (!ctx) return fail(RBF_E_INVALID, "ctx is NULL");
     if (dim != 2 && dim != 3) return fail(RBF_E_INVALID, "dim must be 2 or 3");
@@ -446,11 +462,8 @@ rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const d
     if (n_v < 0 || n_v > (int64_t(1) << 31) - 1) return fail(RBF_E_INVALID, "n_v out of range");
     RBF_TRY(check_precision(precision, level_precision, n_levels));
     if (!basis_valid(basis)) return fail(RBF_E_INVALID, "unknown basis %d", basis);
-    if (n_v == 0) return RBF_OK;
-    if (!xv || !dwall || !dv || (level_off[n_levels] > level_off[0] && (!xc || !alpha)))
+    if (n_v > 0 && (!xv || !dwall || !dv || (level_off[n_levels] > level_off[0] && (!xc || !alpha))))
         return fail(RBF_E_INVALID, "NULL device array");
-    RBF_HIP(hipSetDevice(ctx->device));
-    SumProblem pb;
     pb.dim = dim;
     pb.n_levels = n_levels;
     for (int l = 0; l < n_levels; ++l)
@@ -466,7 +479,42 @@ rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const d
     pb.sign = -1.0;
     pb.precision = precision;
     pb.basis = basis;
+    return RBF_OK;
+}
+
+rbf_status rbf_volume_update(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
+                             const double *D, const int32_t *level_off, int64_t ld_ctrl,
+                             const double *xc, const double *alpha, int64_t n_v, const double *xv,
+                             const double *dwall, double *dv, int32_t precision,
+                             const int32_t *level_precision, int32_t basis, void *stream)
+{
+    SumProblem pb;
+    RBF_TRY(volume_problem(ctx, dim, n_levels, radius, D, level_off, ld_ctrl, xc, alpha, n_v, xv, dwall, dv,
+                           precision, level_precision, basis, pb));
+    if (n_v == 0) return RBF_OK;
+    RBF_HIP(hipSetDevice(ctx->device));
     return run_kernel_sum(ctx, pb, (hipStream_t)stream);
+}
+
+rbf_status rbf_volume_update_noalloc(rbf_ctx ctx, int32_t dim, int32_t n_levels, const double *radius,
+                                     const double *D, const int32_t *level_off, int64_t ld_ctrl,
+                                     const double *xc, const double *alpha, int64_t n_v, const double *xv,
+                                     const double *dwall, double *dv, int32_t precision,
+                                     const int32_t *level_precision, int32_t basis, void *stream)
+{
+    SumProblem pb;
+    RBF_TRY(volume_problem(ctx, dim, n_levels, radius, D, level_off, ld_ctrl, xc, alpha, n_v, xv, dwall, dv,
+                           precision, level_precision, basis, pb));
+    if (n_v > RBF_NOALLOC_MAX_POINTS)
+        return fail(RBF_E_INVALID, "n_v = %lld exceeds RBF_NOALLOC_MAX_POINTS (%d) of the allocation-free call",
+                    (long long)n_v, RBF_NOALLOC_MAX_POINTS);
+    if (!ctx->noalloc_scratch) return fail(RBF_E_DEVICE, "no fixed scratch on device %d", ctx->device);
+    if (n_v == 0) return RBF_OK;
+    RBF_HIP(hipSetDevice(ctx->device));
+    SumScratch sc;
+    sc.base = ctx->noalloc_scratch;
+    sc.bytes = RBF_NOALLOC_SCRATCH_BYTES;
+    return run_kernel_sum(ctx, pb, (hipStream_t)stream, &sc);
 }
 
 rbf_status rbf_evaluate(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c, int64_t ld_ctrl,

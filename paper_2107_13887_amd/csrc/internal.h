@@ -193,6 +193,7 @@ struct rbf_ctx_s {
     std::mutex geom_mu;
     std::unordered_map<rbf_geom, std::unique_ptr<rbf::Geometry>> geoms;
     int n_cu = 256;
+    void *noalloc_scratch = nullptr;   // this device's fixed scratch array (device address)
     // Co-residency budget of the persistent greedy kernels running at once (workgroups).
     std::mutex coop_mu;
     std::condition_variable coop_cv;
@@ -243,9 +244,21 @@ struct SumProblem {
     Geometry *geom = nullptr;            // resident geometry, whose cached row-group order the launch uses
 };
 
+// A caller's fixed device area for the scratch of one kernel sum (the allocation-free entry point).
+struct SumScratch {
+    void *base = nullptr;
+    size_t bytes = 0;
+};
+
 // Enqueues the whole evaluation on `s`; scratch comes from the pool and is released
-// stream-ordered, so the call does not wait for the device.
-rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s);
+// stream-ordered, so the call does not wait for the device. With ext, the scratch is carved from
+// ext instead (fewer control-list splits if their partial sums would not fit) and the call
+// allocates nothing, records no timer events and counts no pairs.
+rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s, const SumScratch *ext = nullptr);
+
+// ---- allocation-free entry point (noalloc.hip) ---------------------------------------------------
+// Device address of the library's fixed scratch array on the current device.
+rbf_status noalloc_scratch_address(void **ptr);
 
 // ---- greedy (greedy.hip) ------------------------------------------------------------------------
 // warm (optional): per-level resident Newton bases; a level whose seeds equal the cached control

@@ -36,7 +36,7 @@ const ShapeEnv &shape_env()
 
 }  // namespace
 
-rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
+rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s, const SumScratch *ext)
 {
     const int DIM = pb.dim;
     if (pb.n_p == 0) return RBF_OK;
@@ -63,6 +63,18 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     a.n_work = pb.n_p;
 
     DevBuf work, nwork, partial, counts;
+    // Scratch from the pool, or carved in 256-byte steps from the caller's fixed area (the
+    // allocation-free entry point: then no pool, no timer events, no pair counter).
+    char *ext_at = ext ? static_cast<char *>(ext->base) : nullptr;
+    size_t ext_left = ext ? ext->bytes : 0;
+    auto carve = [&](size_t bytes) -> void * {
+        const size_t b = (bytes + 255) & ~size_t(255);
+        if (b > ext_left) return nullptr;
+        void *p = ext_at;
+        ext_at += b;
+        ext_left -= b;
+        return p;
+    };
     int64_t n_rows = pb.n_p;    // rows the kernel-sum grid covers
     if (pb.dwall && pb.n_active >= 0) {
         // Resident geometry: results go out through perm. The grid covers every point; the
@@ -72,17 +84,28 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
         a.n_live = pb.n_active;
         a.block_box = pb.block_box;
     } else if (pb.dwall) {
-        RBF_TRY(nwork.get(ctx->pool.get(), sizeof(int64_t), s));
-        {
-            const int64_t nb = (pb.n_p + CBLK - 1) / CBLK;
+        const int64_t nb = (pb.n_p + CBLK - 1) / CBLK;
+        int64_t *nw = nullptr;
+        int32_t *wk = nullptr, *cn = nullptr;
+        if (ext) {
+            nw = static_cast<int64_t *>(carve(sizeof(int64_t)));
+            wk = static_cast<int32_t *>(carve(sizeof(int32_t) * pb.n_p));
+            cn = static_cast<int32_t *>(carve(sizeof(int32_t) * nb));
+            if (!nw || !wk || !cn)
+                return fail(RBF_E_INVALID, "%lld points need more than the %llu bytes of fixed scratch",
+                            (long long)pb.n_p, (unsigned long long)ext->bytes);
+        } else {
+            RBF_TRY(nwork.get(ctx->pool.get(), sizeof(int64_t), s));
             RBF_TRY(work.get(ctx->pool.get(), sizeof(int32_t) * pb.n_p, s));
             RBF_TRY(counts.get(ctx->pool.get(), sizeof(int32_t) * nb, s));
-            launch_reduce(pb.dwall, pb.n_p, dmax, counts.as<int32_t>(), nwork.as<int64_t>(), work.as<int32_t>(),
-                          pb.out, DIM, s);
-            a.work = work.as<int32_t>();
+            nw = nwork.as<int64_t>();
+            wk = work.as<int32_t>();
+            cn = counts.as<int32_t>();
         }
+        launch_reduce(pb.dwall, pb.n_p, dmax, cn, nw, wk, pb.out, DIM, s);
         RBF_HIP(hipGetLastError());
-        a.n_work_dev = nwork.as<int64_t>();
+        a.work = wk;
+        a.n_work_dev = nw;
     }
 
     // Launch shape: P points per lane; split the control lists when there are too few blocks.
@@ -102,6 +125,8 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
     int S = (int)std::max<int64_t>(1, std::min<int64_t>((target + nbx - 1) / nbx, nc_max / 128));
     S = std::min(S, env.max_split > 0 ? env.max_split : 64);
     if (env.split > 0) S = env.split;
+    // Fixed scratch: fewer splits while their partial sums do not fit (one split needs none).
+    while (ext && S > 1 && sizeof(double) * (size_t)S * DIM * n_rows + 255 > ext_left) --S;
     a.n_split = S;
     // Resident geometry: workgroups take the row groups heaviest first, dealt across the compute
     // units (RBF_KSUM_ORDER=0: stored order).
@@ -110,19 +135,23 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s)
         if (!(e && e[0] == '0')) RBF_TRY(resident_order(ctx, *pb.geom, pb, P, nbx, s, &a.order));
     }
     if (S > 1) {
-        RBF_TRY(partial.get(ctx->pool.get(), sizeof(double) * (size_t)S * DIM * n_rows, s));
-        a.partial = partial.as<double>();
+        if (ext) {
+            a.partial = static_cast<double *>(carve(sizeof(double) * (size_t)S * DIM * n_rows));
+        } else {
+            RBF_TRY(partial.get(ctx->pool.get(), sizeof(double) * (size_t)S * DIM * n_rows, s));
+            a.partial = partial.as<double>();
+        }
         a.ld_part = n_rows;
     }
     const dim3 grid((unsigned)nbx, (unsigned)S);
     const char *name = pb.dwall ? (mixed ? "volume_ksum_mixed" : "volume_ksum_fp64")
                                 : (mixed ? "surface_ksum_mixed" : "surface_ksum_fp64");
-    a.pairs = ctx->timers.counter(name);
-    hipEvent_t t0;
-    ctx->timers.begin(&t0, s);
+    a.pairs = ext ? nullptr : ctx->timers.counter(name);
+    hipEvent_t t0 = nullptr;
+    if (!ext) ctx->timers.begin(&t0, s);
     launch_sum(a, grid, DIM, P, mixed, pb.basis, s);
     RBF_HIP(hipGetLastError());
-    ctx->timers.end(name, t0, s);
+    if (!ext) ctx->timers.end(name, t0, s);
     if (S > 1) {
         const int gf = (int)std::min<int64_t>((n_rows + BLOCK - 1) / BLOCK, 8192);
         launch_finalize(a, DIM, gf, s);

@@ -105,6 +105,9 @@ _SIGS = {
     "rbf_volume_update": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
                                  ctypes.POINTER(_i32), _i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32,
                                  ctypes.POINTER(_i32), _i32, _vp]),
+    "rbf_volume_update_noalloc": (_i32, [_vp, _i32, _i32, ctypes.POINTER(_f64), ctypes.POINTER(_f64),
+                                         ctypes.POINTER(_i32), _i64, _vp, _vp, _i64, _vp, _vp, _vp, _i32,
+                                         ctypes.POINTER(_i32), _i32, _vp]),
     "rbf_evaluate": (_i32, [_vp, _i32, _f64, _i64, _i64, _vp, _vp, _i64, _vp, _vp, _f64, _vp, _i32, _i32,
                             _vp]),
     "rbf_geom_create": (_i32, [_vp, _i32, _i64, _vp, _i64, _vp, _vp, ctypes.POINTER(_vp)]),
@@ -418,6 +421,33 @@ def rbf_volume_update(ctx: int, radius: Sequence[float], D: Sequence[float], lev
     _check(lib().rbf_volume_update(ctx, dim, nl, r, d, off, ldc, pxc, pa, n_v, pxv, pd, pdv,
                                    prec, levels, _basis(basis), _stream(stream)),
            "rbf_volume_update")
+    return dv
+
+
+def rbf_volume_update_noalloc(ctx: int, radius: Sequence[float], D: Sequence[float],
+                              level_off: Sequence[int], xc, alpha, xv, dwall, dv, precision="fp64",
+                              stream=None, basis: str = "c2"):
+    """rbf_volume_update through the allocation-free entry point: the caller passes dv, and the
+    library's fixed device scratch replaces its pool (calls overlapping on one GPU race)."""
+    dim, n_v = xv.shape
+    nl = len(radius)
+    if len(level_off) != nl + 1:
+        raise ValueError("level_off must have n_levels + 1 entries")
+    D = list(D) if len(D) == nl else [float(D[0])] * nl
+    pxc, ldc = _dev(xc, "xc", dim, None, allow_ld=True)
+    pa, lda = _dev(alpha, "alpha", dim, None, allow_ld=True)
+    if ldc != lda:
+        raise ValueError("xc and alpha must share a leading dimension")
+    if int(level_off[-1]) > xc.shape[1]:
+        raise ValueError("level_off exceeds the control arrays")
+    pxv, _ = _dev(xv, "xv", dim, n_v)
+    pd, _ = _dev(dwall, "dwall", None, n_v)
+    pdv, _ = _dev(dv, "dv", dim, n_v)
+    r, d, off = _level_arrays(radius, D, level_off)
+    prec, levels = _precision(precision, nl)
+    _check(lib().rbf_volume_update_noalloc(ctx, dim, nl, r, d, off, ldc, pxc, pa, n_v, pxv, pd, pdv,
+                                           prec, levels, _basis(basis), _stream(stream)),
+           "rbf_volume_update_noalloc")
     return dv
 
 
