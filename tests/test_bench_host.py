@@ -33,7 +33,7 @@ def test_committed_traffic_matches_current_kernel(workload, precision):
     path = os.path.join(ROOT, "profiles", f"traffic_volume_ksum_{workload}_{precision}.txt")
     text = open(path).read()
     assert f"ksum_source_sha256_16: {bench.kernel_source_hash()}" in text
-    dim, n_red, n_rows = {"cfg1": (2, 243304, 400384), "cfg2": (3, 2832398, 4000256)}[workload]
+    dim, n_red, n_rows = {"cfg1": (2, 244584, 400384), "cfg2": (3, 2542809, 4002304)}[workload]
     algo = n_red * ((dim + 1) * 8 + 4) + (n_rows - n_red) * 4 + n_rows * dim * 8
     t = bench.measured_traffic(workload, precision)
     assert t is not None and algo / 1.5 < t < algo * 1.5
