@@ -285,10 +285,21 @@ def test_greedy_long_level_with_several_tiles_per_workgroup(gctx, orc, monkeypat
 
 
 @pytest.mark.parametrize("mode", ["lean", "cg", "kernels"])
-def test_greedy_every_schedule_matches_oracle(gctx, orc, monkeypatch, mode):
-    """The three schedules of an iteration (persistent kernel with one barrier, cooperative-groups
-    grid barriers, two launches) select the oracle's control points."""
+@pytest.mark.parametrize("case", ["cfg0", "cfg1"])
+def test_greedy_every_schedule_matches_oracle(gctx, orc, monkeypatch, mode, case):
+    """Every schedule of an iteration selects the oracle's control points: the persistent kernel
+    with one agent-scope barrier per iteration, cooperative-groups grid barriers, two launches.
+    The 2D airfoil with two seeds (7 tiles) and the multi-level airfoil (63 tiles)."""
     monkeypatch.setenv("RBF_GREEDY_MODE", mode)
-    w = synth.workload_cfg0()
-    ref, cs = _greedy_both(gctx, orc, w)
-    _check_same(orc, w, ref, cs)
+    w = synth.workload_cfg0() if case == "cfg0" else synth.workload_cfg1()
+    if case not in _SCHEDULE_REF:
+        _SCHEDULE_REF[case] = orc.greedy(w.dim, w.xs, w.ds, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
+                                         seeds=w.seeds)
+    print(f"case {case} schedule {mode}", flush=True)
+    cs = rbfdef.rbf_greedy_select(gctx, to_dev(w.xs), to_dev(w.ds), w.radius, w.eps, rho=w.rho,
+                                  cap=w.cap_total(), seeds=w.seeds)
+    torch.cuda.synchronize()
+    _check_same(orc, w, _SCHEDULE_REF[case], cs)
+
+
+_SCHEDULE_REF = {}
