@@ -582,6 +582,73 @@ def side_block(ctx, name, precision, basis, steps, warmup, with_oracle):
     return m, b, ref
 
 
+def seeded_start_block(ctx, m, basis, scale=1.25):
+    """The next icing step (displacement x scale) seeded with this step's control sets and no
+    resident basis, timed both ways: each level's seeds started from the blocked FP64 MFMA
+    Cholesky of their Phi_CC and the blocked MFMA triangular solve for their Newton basis, and
+    appended one iteration each. Same control sets either way (checked)."""
+    import numpy as np
+    import torch
+
+    from paper_2107_13887_amd import rbfdef
+
+    w, cs = m["w"], m["cs"]
+    used = cs.n_levels_used
+    ctrl = cs.ctrl_idx[: cs.total].cpu().numpy()
+    off = cs.level_off
+    seeds = [[int(p) for p in ctrl[off[l]:off[l + 1]]] for l in range(used)]
+    seeds += [[] for _ in range(w.n_levels - used)]
+    ds2 = (scale * m["ds"]).contiguous()
+    call = lambda: rbfdef.rbf_greedy_select(ctx, m["xs"], ds2, w.radius, w.eps, rho=w.rho, cap=w.cap_total(),
+                                            seeds=seeds, precision="fp64", want_residual=False, basis=basis)
+    res = {}
+    for start, reps in (("factor", 3), ("append", 1)):
+        os.environ["RBF_SEED_START"] = start
+        try:
+            call()
+            torch.cuda.synchronize()
+            if start == "factor":
+                rbfdef.rbf_ctx_set_timing(ctx, True)
+            times = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                c2 = call()
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            if start == "factor":
+                dev = {k: rbfdef.rbf_ctx_kernel_time(ctx, k) for k in ("seed_start", "seed_factor", "seed_basis")}
+                rbfdef.rbf_ctx_set_timing(ctx, False)
+        finally:
+            os.environ.pop("RBF_SEED_START", None)
+        res[start] = (statistics.median(times), c2.ctrl_idx[: c2.total].cpu().numpy(), c2.n_iterations)
+    flops_chol = flops_basis = 0
+    g = (w.n_s + 63) // 64
+    for sl in seeds:
+        nb = (len(sl) + 63) // 64
+        if len(sl) < 32:
+            continue
+        flops_chol += sum((nb - kb - 1) * (nb - kb) // 2 for kb in range(nb)) * 2 * 64 ** 3
+        flops_basis += g * (nb * (nb - 1) // 2 + nb) * 2 * 64 ** 3
+    per = lambda k: dev[k][0] / 3   # per call (three timed calls), summed over its levels
+    mf_ms = per("seed_factor") + per("seed_basis")
+    return {
+        "workload": f"{w.name} next icing step (displacement x {scale}) seeded with this step's control "
+                    "sets, no resident basis",
+        "seeds_per_level": [len(sl) for sl in seeds],
+        "greedy_call_ms": {"factor": res["factor"][0] * 1e3, "append": res["append"][0] * 1e3},
+        "seeded_start_ms_device": per("seed_start"),
+        "seed_factor_ms_device": per("seed_factor"),
+        "seed_basis_ms_device": per("seed_basis"),
+        "append_minus_factor_ms": (res["append"][0] - res["factor"][0]) * 1e3,
+        "identical_selections": bool(np.array_equal(res["factor"][1], res["append"][1])),
+        "argmax_iterations_after_seeds": res["factor"][2],
+        "mfma_flops": {"cholesky_trailing": flops_chol, "basis_trsm": flops_basis},
+        "mfma_tflops_in_factor_and_basis": (flops_chol + flops_basis) / (mf_ms / 1e3) / 1e12 if mf_ms > 0 else None,
+        "frac_of_fp64_mfma_peak": (flops_chol + flops_basis) / (mf_ms / 1e3) / 78.6e12 if mf_ms > 0 else None,
+        "timers_note": "device times per call (hipEvents on the launch stream), summed over the levels",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -656,6 +723,7 @@ def main():
         flops = nn ** 3 / 3 + 2 * w.dim * nn * nn
         dense.append({"points": nn, "set": label, "ms": ms, "tflops": flops / (ms / 1e3) / 1e12,
                       "frac_of_fp64_mfma": flops / (ms / 1e3) / 78.6e12})
+    seeded = seeded_start_block(ctx, m, args.basis)
     # The greedy's per-iteration floor: one 64-point tile, every point selected (eps 0), so each
     # iteration is all synchronization and no streaming.
     n_tiny = min(64, w.n_s)
@@ -702,6 +770,7 @@ def main():
         "greedy_iteration_floor_us": floor_us,
         "greedy_error_curve": error_curve(cs, w),
         "dense_solve": dense,
+        "seeded_start": seeded,
         "selection_identical_to_oracle": ref["same"] if ref else None,
         "selection_check": ref["check"] if ref else None,
         "precision_study": study,

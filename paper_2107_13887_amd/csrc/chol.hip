@@ -14,6 +14,8 @@
 // the contributions of the finished blocks as each is published, and multiplies by the inverse,
 // so the chain from one block to the next is one flag, one 64x64 product and one 64x64 product.
 // A non-positive pivot raises a device flag reported as RBF_E_NOT_SPD.
+// The same factorization starts a greedy level from given control points (the seeds), followed by
+// a blocked FP64 MFMA triangular solve for their Newton basis at every surface point.
 #include <cmath>
 #include <cstdlib>
 
@@ -26,6 +28,7 @@ namespace {
 
 constexpr int NB = 64;
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ double sqrt_pos(double a)
 {
@@ -158,19 +161,16 @@ __global__ __launch_bounds__(NB) void c_diag(double *A, int64_t lda, int64_t k0,
     diag_factor(A, lda, k0, bad, T, col);
 }
 
-// acc(64x64, this wave's 32x32 quarter) = Ablk(64x64) * Bblk(64x64)^T from LDS via FP64 MFMA.
+// acc(64x64, this wave's 32x32 quarter) += Ablk(64x64) * Bblk(64x64)^T from LDS via FP64 MFMA.
 // MFMA 16x16x4 f64: lane l supplies A[l % 16][l / 16] and B^T[l / 16][l % 16]; result element
 // v of lane l is D[l / 16 + 4 v][l % 16] (rows interleaved across the four result registers).
-__device__ __forceinline__ void tile_abt(const double (*Ab)[NB + 1], const double (*Bb)[NB + 1],
-                                         d4 acc[2][2])
+__device__ __forceinline__ void tile_abt_acc(const double (*Ab)[NB + 1], const double (*Bb)[NB + 1],
+                                             d4 acc[2][2])
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-#pragma unroll
-        for (int c = 0; c < 2; ++c) acc[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
     for (int kk = 0; kk < NB; kk += 4) {
         double af[2], bf[2];
 #pragma unroll
@@ -183,6 +183,16 @@ __device__ __forceinline__ void tile_abt(const double (*Ab)[NB + 1], const doubl
             for (int c = 0; c < 2; ++c)
                 acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[r], bf[c], acc[r][c], 0, 0, 0);
     }
+}
+
+// acc = Ablk * Bblk^T (as above, from zero).
+__device__ __forceinline__ void tile_abt(const double (*Ab)[NB + 1], const double (*Bb)[NB + 1], d4 acc[2][2])
+{
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+    tile_abt_acc(Ab, Bb, acc);
 }
 
 // Panel: L_ik = A_ik L_kk^-T for every row block i below k. One wave per row block, lane r holds
@@ -392,6 +402,201 @@ __global__ __launch_bounds__(NB) void c_bwd_chain(ChainArgs a, double *x)
     tc_publish(&a.st[CH_HDR + a.nblk + kb]);
 }
 
+// ---- seeded level start: the Newton basis of a given control set -----------------------------
+// A level that starts from n given control points (a warm start whose resident basis is gone, or
+// a call with seeds) needs L with L L^T = Phi_CC and V = Phi_sC L^-T at every surface point. The
+// factor comes from the blocked MFMA Cholesky above; V from a blocked triangular solve by
+// 64-column blocks, left-looking, one workgroup per tile of 64 surface points:
+//   acc   = Phi(tile, C_K) - sum_{J < K} V(tile, J) L_KJ^T      (FP64 MFMA, 64 x 64 x 64 per J)
+//   V(tile, K) = acc Dinv_K^T                                    (FP64 MFMA, Dinv_K = inv(L_KK))
+// Phi(tile, C_K) is evaluated in the workgroup, exactly as the greedy's own update evaluates phi,
+// so the only differences from appending the points one by one are the order of the sums and the
+// use of the diagonal blocks' inverses.
+
+// Dinv_kb = inv(L_kb,kb) for every diagonal block of the factored padded matrix, row-major.
+__global__ __launch_bounds__(NB) void c_diag_inverse(const double *A, int64_t lda, double *dinv)
+{
+    __shared__ double Ls[NB][NB + 1];
+    __shared__ double Dv[NB][NB + 1];
+    __shared__ double rl[NB];
+    const int64_t k0 = (int64_t)blockIdx.x * NB;
+    block_to_lds(A, lda, k0, k0, Ls);
+    __syncthreads();
+    tc_tri_inverse(Ls, Dv, rl);
+    __syncthreads();
+    double *dk = dinv + (int64_t)blockIdx.x * NB * NB;
+#pragma unroll 8
+    for (int r = 0; r < NB; ++r) dk[r * NB + threadIdx.x] = Dv[r][threadIdx.x];
+}
+
+// Packed rows of the factor: Lp[i (i + 1) / 2 + j] = L[i][j], j <= i < n.
+__global__ __launch_bounds__(256) void c_pack(const double *A, int64_t lda, int64_t n, double *Lp)
+{
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x)
+        for (int64_t j = threadIdx.x; j <= i; j += 256) Lp[(i * (i + 1)) / 2 + j] = A[i * lda + j];
+}
+
+// phi(||x_i - c_j|| / R) as the greedy's update forms it: the squared distance summed in order
+// without contraction, an IEEE root and a division by R, exactly zero from eta = 1 on.
+template <int DIM>
+__device__ __forceinline__ double phi_seed(const double (&x)[DIM], const double (&c)[DIM], double R,
+                                           int32_t basis)
+{
+    double s = 0.0;
+    {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const double d = x[k] - c[k];
+            s = s + d * d;
+        }
+    }
+    const double eta = sqrt(s) / R;
+    return eta >= 1.0 ? 0.0 : wendland(basis, eta);
+}
+
+// V(tile, 0:n) for one tile of 64 surface points per workgroup (see above). Blocks of V and L
+// stream through LDS with the next block's loads in flight during the current block's MFMAs.
+// V is tile-major: V(i, j) at ((i / 64) ldt + j) 64 + i % 64; rows past n_s take the last
+// point's coordinates and are never read as results.
+template <int DIM>
+__global__ __launch_bounds__(256, 2) void c_seed_basis(const double *xs, int64_t n_s, const double *xc, int64_t n,
+                                                    double R, int32_t basis, const double *A, int64_t lda,
+                                                    const double *dinv, double *V, int64_t ldt)
+{
+    __shared__ double va[NB][NB + 1];
+    __shared__ double lb[NB][NB + 1];
+    __shared__ double xt[DIM][NB];
+    __shared__ double ck[DIM][NB];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t tile = blockIdx.x;
+    const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+    const int64_t nblk = (n + NB - 1) / NB;
+    double *vt = V + tile * ldt * NB;
+    if (t < NB) {
+        const int64_t i = min(tile * NB + t, n_s - 1);
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xt[k][t] = xs[k * n_s + i];
+    }
+    for (int64_t kb = 0; kb < nblk; ++kb) {
+        d4 acc[2][2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) acc[r][c] = d4{0.0, 0.0, 0.0, 0.0};
+        // Earlier blocks: acc += V(tile, J) L_kb,J^T. Pair e = t + 256 q (q < 8) of a block holds
+        // elements 2e and 2e + 1: column e / 32 and rows 2 (e % 32) + {0, 1} of V's block (one
+        // contiguous 32 KB region), row e / 32 and columns 2 (e % 32) + {0, 1} of L's block
+        // (64 contiguous 512-byte rows). 16-byte loads, the next block's in flight during the MFMAs.
+        const int pr = t >> 5, pc = (t & 31) * 2;   // pair q: V column / L row pr + 8 q, offset pc
+        const d2 *vsrc = reinterpret_cast<const d2 *>(vt) + t;
+        const double *lsrc = A + (kb * NB + pr) * lda + pc;
+        d2 pv[8], pl[8];
+        if (kb > 0) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                pv[q] = vsrc[256 * q];
+                pl[q] = *reinterpret_cast<const d2 *>(lsrc + 8 * q * lda);
+            }
+        }
+        for (int64_t jb = 0; jb < kb; ++jb) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                va[pc][pr + 8 * q] = pv[q].x;
+                va[pc + 1][pr + 8 * q] = pv[q].y;
+                lb[pr + 8 * q][pc] = pl[q].x;
+                lb[pr + 8 * q][pc + 1] = pl[q].y;
+            }
+            __syncthreads();
+            if (jb + 1 < kb) {
+                vsrc += NB * NB / 2;
+                lsrc += NB;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    pv[q] = vsrc[256 * q];
+                    pl[q] = *reinterpret_cast<const d2 *>(lsrc + 8 * q * lda);
+                }
+            }
+            tile_abt_acc(va, lb, acc);
+        }
+        // B = Phi(tile, C_kb) - acc into va: phi by element e = t + 256 q (row e % 64, column
+        // e / 64), then each lane subtracts its accumulator entries. Columns past n are zero.
+        __syncthreads();
+        if (t < NB) {
+            const int64_t j = min(kb * NB + t, n - 1);
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) ck[k][t] = xc[k * n + j];
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int q = 0; q < 16; ++q) {
+            const int e = t + 256 * q, row = e & 63, col = e >> 6;
+            double xx[DIM], cc[DIM];
+#pragma unroll
+            for (int k = 0; k < DIM; ++k) {
+                xx[k] = xt[k][row];
+                cc[k] = ck[k][col];
+            }
+            va[row][col] = kb * NB + col < n ? phi_seed<DIM>(xx, cc, R, basis) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int col = c0 + c * 16 + (lane & 15);
+                if (kb * NB + col < n)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) va[r0 + r * 16 + (lane >> 4) + 4 * v][col] -= acc[r][c][v];
+            }
+        const double *dk = dinv + kb * NB * NB;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = t + 256 * q;
+            lb[e >> 6][e & 63] = dk[e];
+        }
+        __syncthreads();
+        // V(tile, kb)[row][c] = sum_m B[row][m] Dinv[c][m], staged column-major for the stores.
+        tile_abt(va, lb, acc);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    va[c0 + c * 16 + (lane & 15)][r0 + r * 16 + (lane >> 4) + 4 * v] = acc[r][c][v];
+        __syncthreads();
+        const int64_t live_cols = min<int64_t>(NB, n - kb * NB);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int e = t + 256 * q;
+            if ((e >> 6) < live_cols) vt[kb * NB * NB + e] = va[e >> 6][e & 63];
+        }
+    }
+}
+
+// Phi_cc of the n points xc ([dim][n]) on the padded row-major matrix A (lda = 64 ceil(n / 64)),
+// factored in place into its lower Cholesky factor (launches only). A non-positive pivot sets *bad.
+template <int DIM>
+void launch_factor(double radius, int64_t n, const double *xc, int32_t basis, double *A, int64_t lda,
+                   int32_t *bad, hipStream_t s)
+{
+    const int64_t nblk = lda / NB;
+    hipLaunchKernelGGL(c_build<DIM>, dim3((unsigned)std::min<int64_t>(lda, 8192)), dim3(256), 0, s,
+                       xc, n, lda, 1.0 / radius, basis, A);
+    for (int64_t kb = 0; kb < nblk; ++kb) {
+        const int64_t k0 = kb * NB, rest = nblk - kb - 1;
+        if (kb == 0) hipLaunchKernelGGL(c_diag, dim3(1), dim3(NB), 0, s, A, lda, k0, bad);
+        if (rest > 0) {
+            hipLaunchKernelGGL(c_panel, dim3((unsigned)rest), dim3(NB), 0, s, A, lda, k0);
+            hipLaunchKernelGGL(c_trailing, dim3((unsigned)(rest * (rest + 1) / 2)), dim3(256), 0, s, A, lda,
+                               k0, rest, bad);
+        }
+    }
+}
+
 template <int DIM>
 rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, const double *dsc,
                       double *alpha, int32_t basis, hipStream_t s)
@@ -408,17 +613,7 @@ rbf_status solve_impl(rbf_ctx ctx, double radius, int64_t n, const double *xc, c
     double *A = bA.as<double>();
     int32_t *st = bSt.as<int32_t>();
     RBF_HIP(hipMemsetAsync(st, 0, st_bytes, s));
-    hipLaunchKernelGGL(c_build<DIM>, dim3((unsigned)std::min<int64_t>(lda, 8192)), dim3(256), 0, s,
-                       xc, n, lda, 1.0 / radius, basis, A);
-    for (int64_t kb = 0; kb < nblk; ++kb) {
-        const int64_t k0 = kb * NB, rest = nblk - kb - 1;
-        if (kb == 0) hipLaunchKernelGGL(c_diag, dim3(1), dim3(NB), 0, s, A, lda, k0, st + 3);
-        if (rest > 0) {
-            hipLaunchKernelGGL(c_panel, dim3((unsigned)rest), dim3(NB), 0, s, A, lda, k0);
-            hipLaunchKernelGGL(c_trailing, dim3((unsigned)(rest * (rest + 1) / 2)), dim3(256), 0, s, A, lda,
-                               k0, rest, st + 3);
-        }
-    }
+    launch_factor<DIM>(radius, n, xc, basis, A, lda, st + 3, s);
     RBF_HIP(hipGetLastError());
     ChainArgs ca{};
     ca.A = A;
@@ -455,6 +650,32 @@ rbf_status run_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_
 {
     return dim == 2 ? solve_impl<2>(ctx, radius, n_c, xc, dsc, alpha, basis, s)
                     : solve_impl<3>(ctx, radius, n_c, xc, dsc, alpha, basis, s);
+}
+
+rbf_status seed_factor(int32_t dim, double radius, int32_t basis, int64_t n, const double *xc, double *A,
+                       int64_t lda, double *dinv, int32_t *bad, hipStream_t s)
+{
+    if (dim == 2) launch_factor<2>(radius, n, xc, basis, A, lda, bad, s);
+    else launch_factor<3>(radius, n, xc, basis, A, lda, bad, s);
+    hipLaunchKernelGGL(c_diag_inverse, dim3((unsigned)(lda / NB)), dim3(NB), 0, s, (const double *)A, lda, dinv);
+    RBF_HIP(hipGetLastError());
+    return RBF_OK;
+}
+
+rbf_status seed_basis(int32_t dim, const double *xs, int64_t n_s, const double *xc, int64_t n, double radius,
+                      int32_t basis, const double *A, int64_t lda, const double *dinv, double *V, int64_t ldt,
+                      double *Lpack, hipStream_t s)
+{
+    const unsigned g = (unsigned)((n_s + NB - 1) / NB);
+    hipLaunchKernelGGL(c_pack, dim3((unsigned)std::min<int64_t>(n, 8192)), dim3(256), 0, s, A, lda, n, Lpack);
+    if (dim == 2)
+        hipLaunchKernelGGL(c_seed_basis<2>, dim3(g), dim3(256), 0, s, xs, n_s, xc, n, radius, basis, A, lda, dinv,
+                           V, ldt);
+    else
+        hipLaunchKernelGGL(c_seed_basis<3>, dim3(g), dim3(256), 0, s, xs, n_s, xc, n, radius, basis, A, lda, dinv,
+                           V, ldt);
+    RBF_HIP(hipGetLastError());
+    return RBF_OK;
 }
 
 }  // namespace rbf

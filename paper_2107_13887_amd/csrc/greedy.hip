@@ -23,6 +23,13 @@
 // impossible) the two phases run as two kernel launches per iteration.
 // Reductions run in a fixed order; squared norms are formed without fused multiply-adds so they
 // equal the textbook formula term by term.
+//
+// Seeded levels. A level handed its first control points (a warm start from the previous icing
+// step's set, or the caller's seeds) starts from the resident basis of the same points when one is
+// kept; otherwise, from SEED_FACTOR_MIN seeds on, from L = chol(Phi_CC) (blocked, FP64 MFMA) and
+// V = Phi_sC L^-T (blocked triangular solves, FP64 MFMA) formed at once, rather than by appending
+// the seeds one iteration each. Either way y = L^-1 dS_C and E = dS - V y follow, and the level
+// continues with its argmax iterations.
 #include <hip/hip_cooperative_groups.h>
 
 #include <algorithm>
@@ -44,6 +51,7 @@ constexpr int UWAVES = 4;     // waves per workgroup, each a slice of the dot pr
 constexpr int NT = UPB * UWAVES;
 constexpr int LCHUNK = 2048;  // Newton row entries staged per LDS pass
 constexpr int64_t LEAN_MAX_TILES = 256;   // largest surface (in tiles) run by the persistent kernel
+constexpr int64_t SEED_FACTOR_MIN = 32;   // fewest seeds of a level started from the blocked factor
 
 struct GState {
     int64_t n;        // finished columns (control points) of the level
@@ -912,6 +920,18 @@ __global__ __launch_bounds__(256) void g_seed_rhs(const double *r, int64_t n_s, 
     }
 }
 
+// xc[k][j] = xs[k][seeds[j]]: the seeds' coordinates, gathered for the dense factor.
+template <int DIM>
+__global__ __launch_bounds__(256) void g_gather_seeds(const double *xs, int64_t n_s, const int64_t *seeds, int64_t n,
+                                                      double *xc)
+{
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = seeds[j];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xc[k * n + j] = xs[k * n_s + p];
+    }
+}
+
 // E = r - V y over all surface points for the n resident columns (Newton coefficients y in
 // coef), and the per-tile argmax of ||E_i||^2 over unselected points.
 template <int DIM>
@@ -1101,6 +1121,11 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     // iteration beyond that: there the basis stream is the cost, and fresh launches stream it at
     // about twice the rate of the persistent kernel, whose per-workgroup release and acquire each
     // iteration write back and invalidate the L2 of every XCD.
+    // Seeded starts: blocked factor from SEED_FACTOR_MIN seeds on; RBF_SEED_START=append|factor
+    // forces one form (tests and timing).
+    int64_t seed_factor_min = SEED_FACTOR_MIN;
+    if (const char *e = getenv("RBF_SEED_START"))
+        seed_factor_min = !strcmp(e, "append") ? INT64_MAX : !strcmp(e, "factor") ? 1 : SEED_FACTOR_MIN;
     const char *mode_env = getenv("RBF_GREEDY_MODE");
     const int mode = getenv("RBF_NO_COOP") ? 2
                    : (mode_env && !strcmp(mode_env, "cg")) ? 1
@@ -1165,6 +1190,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
         }
         // Warm start from the resident basis of the same control points: copy V and L, then
         // y = L^-1 r_C and E = r - V y; the level continues from n0 columns.
+        int64_t n_start = 0;   // columns the level starts with (0: its seeds are appended one by one)
+        hipEvent_t seed_timer = nullptr;
         if (warm && l < (int)warm->size()) {
             const LevelCache &lc = (*warm)[l];
             const int64_t n0 = lc.n;
@@ -1177,20 +1204,67 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
                 RBF_HIP(hipMemcpyAsync(a.Lpack, lc.L.ptr, sizeof(double) * (n0 * (n0 + 1) / 2),
                                        hipMemcpyDeviceToDevice, s));
                 RBF_HIP(hipMemcpyAsync(a.ctrl, lc.ctrl.data(), sizeof(int64_t) * n0, hipMemcpyHostToDevice, s));
-                const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n0 + 255) / 256, 1024));
-                hipLaunchKernelGGL(g_seed_rhs<DIM>, dim3(gs), dim3(256), 0, s, R, n_s, a.ctrl, n0, R2, cols, a.sel);
-                for (int64_t b0 = 0; b0 < n0; b0 += 64) {
-                    const int64_t b1 = std::min<int64_t>(n0, b0 + 64);
-                    const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n0 - b1 + 255) / 256, 1024));
-                    hipLaunchKernelGGL(g_fwdsolve<DIM>, dim3(gb), dim3(256), 0, s, a.Lpack, R2, cols, a.coef,
-                                       cols, n0, b0, b1);
-                }
-                hipLaunchKernelGGL(g_apply<DIM>, dim3((unsigned)g), dim3(NT), 0, s, a, (const double *)R, n0);
-                hipLaunchKernelGGL(g_set_count, dim3(1), dim3(64), 0, s, st, n0);
-                RBF_HIP(hipGetLastError());
-                a.n_seeds = 0;
-                a.max_iter = a.cap_level - n0 + 2;
+                n_start = n0;
             }
+        }
+        // No resident basis for a level handed enough seeds: L from the blocked FP64 MFMA Cholesky
+        // of the seeds' Phi_CC and V = Phi_sC L^-T from blocked triangular solves, in place of n
+        // single appends. A seed set whose factor meets a non-positive pivot (a repeated or
+        // numerically dependent point) is appended one by one instead, which stops the level at
+        // the breakdown as before.
+        if (n_start == 0 && a.n_seeds >= seed_factor_min && a.n_seeds <= a.cap_level) {
+            const int64_t n0 = a.n_seeds;
+            const int64_t lda0 = (n0 + 63) / 64 * 64;
+            DevBuf bXc, bA, bDinv, bBad;
+            RBF_TRY(bXc.get(pool, sizeof(double) * DIM * (size_t)n0, s));
+            RBF_TRY(bA.get(pool, sizeof(double) * (size_t)lda0 * (size_t)lda0, s));
+            RBF_TRY(bDinv.get(pool, sizeof(double) * 64 * (size_t)lda0, s));
+            RBF_TRY(bBad.get(pool, sizeof(int32_t), s));
+            RBF_HIP(hipMemsetAsync(bBad.ptr, 0, sizeof(int32_t), s));
+            // Device timers (rbf_ctx_set_timing): "seed_factor", "seed_basis", and "seed_start" from
+            // the gather to the level's first error (the pivot check's round trip included).
+            hipEvent_t t_start = nullptr, t_factor = nullptr;
+            ctx->timers.begin(&t_start, s);
+            const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n0 + 255) / 256, 1024));
+            hipLaunchKernelGGL(g_gather_seeds<DIM>, dim3(gs), dim3(256), 0, s, xs, n_s, a.seeds, n0, bXc.as<double>());
+            ctx->timers.begin(&t_factor, s);
+            RBF_TRY(seed_factor(DIM, Rl, prm.basis, n0, bXc.as<const double>(), bA.as<double>(), lda0,
+                                bDinv.as<double>(), bBad.as<int32_t>(), s));
+            ctx->timers.end("seed_factor", t_factor, s);
+            int32_t not_spd = 0;
+            RBF_HIP(hipMemcpyAsync(&not_spd, bBad.ptr, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            RBF_HIP(hipStreamSynchronize(s));
+            if (!not_spd) {
+                hipEvent_t t_basis = nullptr;
+                ctx->timers.begin(&t_basis, s);
+                RBF_TRY(seed_basis(DIM, xs, n_s, bXc.as<const double>(), n0, Rl, prm.basis, bA.as<const double>(),
+                                   lda0, bDinv.as<const double>(), a.V, ldt, a.Lpack, s));
+                ctx->timers.end("seed_basis", t_basis, s);
+                RBF_HIP(hipMemcpyAsync(a.ctrl, a.seeds, sizeof(int64_t) * n0, hipMemcpyDeviceToDevice, s));
+                n_start = n0;
+                seed_timer = t_start;
+            } else {
+                ctx->timers.end("seed_start_not_spd", t_start, s);
+            }
+        }
+        // From a basis of n_start columns: y = L^-1 r_C by blocked forward substitution, then
+        // E = r - V y and the per-tile maxima; the level continues from there.
+        if (n_start > 0) {
+            const int64_t n0 = n_start;
+            const unsigned gs = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n0 + 255) / 256, 1024));
+            hipLaunchKernelGGL(g_seed_rhs<DIM>, dim3(gs), dim3(256), 0, s, R, n_s, a.ctrl, n0, R2, cols, a.sel);
+            for (int64_t b0 = 0; b0 < n0; b0 += 64) {
+                const int64_t b1 = std::min<int64_t>(n0, b0 + 64);
+                const unsigned gb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n0 - b1 + 255) / 256, 1024));
+                hipLaunchKernelGGL(g_fwdsolve<DIM>, dim3(gb), dim3(256), 0, s, a.Lpack, R2, cols, a.coef,
+                                   cols, n0, b0, b1);
+            }
+            hipLaunchKernelGGL(g_apply<DIM>, dim3((unsigned)g), dim3(NT), 0, s, a, (const double *)R, n0);
+            hipLaunchKernelGGL(g_set_count, dim3(1), dim3(64), 0, s, st, n0);
+            RBF_HIP(hipGetLastError());
+            if (seed_timer) ctx->timers.end("seed_start", seed_timer, s);
+            a.n_seeds = 0;
+            a.max_iter = a.cap_level - n0 + 2;
         }
         bool done = false;
         if (coop_max > 0) {

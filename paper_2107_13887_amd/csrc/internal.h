@@ -262,7 +262,9 @@ rbf_status noalloc_scratch_address(void **ptr);
 
 // ---- greedy (greedy.hip) ------------------------------------------------------------------------
 // warm (optional): per-level resident Newton bases; a level whose seeds equal the cached control
-// points (same radius) starts from the cached basis instead of re-appending the seeds.
+// points (same radius) starts from the cached basis. Other levels with enough seeds form their
+// basis from the blocked factor of the seeds' Phi_CC (seed_factor, seed_basis) instead of
+// appending the seeds one at a time.
 // store (optional): receives every level's basis after the call (best effort: a level whose copy
 // cannot be allocated is left empty).
 rbf_status run_greedy(rbf_ctx ctx, const rbf_greedy_params &p, int64_t n_s, const double *xs,
@@ -275,6 +277,17 @@ uint64_t cache_bytes(const std::vector<LevelCache> &levels, int64_t n_s);
 rbf_status run_solve_weights(rbf_ctx ctx, int32_t dim, double radius, int64_t n_c,
                              const double *xc, const double *dsc, double *alpha, int32_t basis,
                              hipStream_t s);
+// Seeded level start (launches only, stream-ordered). seed_factor: Phi_CC of the n points xc
+// ([dim][n]) factored in place on A (row-major, lda = 64 ceil(n / 64), padding identity) by the
+// blocked FP64 MFMA Cholesky, and dinv[kb] = inv(L_kb,kb) (row-major 64 x 64 blocks); a
+// non-positive pivot sets *bad (device int32 the caller zeroed). seed_basis: Lpack = the factor's
+// packed rows (row i at i (i + 1) / 2) and V = Phi_sC L^-T for the n_s surface points, written as
+// columns 0..n-1 of the greedy's tile-major basis (64-point tiles, ldt columns per tile).
+rbf_status seed_factor(int32_t dim, double radius, int32_t basis, int64_t n, const double *xc, double *A,
+                       int64_t lda, double *dinv, int32_t *bad, hipStream_t s);
+rbf_status seed_basis(int32_t dim, const double *xs, int64_t n_s, const double *xc, int64_t n, double radius,
+                      int32_t basis, const double *A, int64_t lda, const double *dinv, double *V, int64_t ldt,
+                      double *Lpack, hipStream_t s);
 
 // ---- validation helpers (capi.cpp) ---------------------------------------------------------------
 rbf_status validate_params(const rbf_greedy_params &p, int64_t n_s);

@@ -498,11 +498,13 @@ uint64_t greedy_footprint(int dim, int64_t n_s, int64_t cap)
 {
     const uint64_t cols = (uint64_t)std::min<int64_t>(n_s, cap);
     const uint64_t rows = (uint64_t)((n_s + 63) / 64) * 64;   // the basis keeps whole 64-point tiles
+    const uint64_t lda = (cols + 63) / 64 * 64;
     return sizeof(double) * (2 * ((cols + 1) * rows + cols * (cols + 1) / 2) + (uint64_t)(3 * dim + 1) * n_s +
                              (uint64_t)(dim + 1) * cols + 2 * (uint64_t)cap) +
            (uint64_t)n_s * 17 + sizeof(int64_t) * (uint64_t)cap + sizeof(double) * (uint64_t)cap * 2 * dim +
            sizeof(double) * ((uint64_t)dim * n_s + (uint64_t)n_s / 256 + 1) +   // FP32 error check
-           sizeof(double) * (uint64_t)dim * n_s + 16 * (uint64_t)(n_s / 64 + 1);  // persistent form's second buffers
+           sizeof(double) * (uint64_t)dim * n_s + 16 * (uint64_t)(n_s / 64 + 1) +  // persistent form's second buffers
+           sizeof(double) * (lda * lda + 64 * lda + (uint64_t)dim * cols) + 256;    // seeded start's dense factor
 }
 
 }  // namespace
