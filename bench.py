@@ -80,9 +80,11 @@ def build_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-# The device code of the volume kernel sum: its kernels and launch wrappers, their argument block
-# and the basis functions they inline. The host planner (ksum_host.cpp) is left out.
-KERNEL_SOURCES = ("ksum.hip", "ksum.h", "basis.h")
+# What decides the volume kernel sum's memory traffic: its kernels and launch wrappers, their
+# argument block, the basis functions they inline, and the resident geometry's stored layout
+# (serve.cpp: the order of the rows decides how the writes through the permutation coalesce).
+# The host planner (ksum_host.cpp) is left out.
+KERNEL_SOURCES = ("ksum.hip", "ksum.h", "basis.h", "serve.cpp")
 
 
 def kernel_source_hash():
@@ -102,9 +104,9 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload, precision):
-    """HBM bytes per launch of the volume kernel-sum, from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when that summary was
-    taken on a different kernel source."""
+    """HBM bytes per launch of the volume kernel-sum, from the committed counter summary (the L2's
+    read and write requests to memory, counted by size: 32, 64 and 128 bytes), or None when that
+    summary was taken on a different kernel source or layout."""
     path = os.path.join(ROOT, "profiles", f"traffic_volume_ksum_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None

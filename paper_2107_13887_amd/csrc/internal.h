@@ -137,6 +137,7 @@ struct Geometry {
     DevBuf xs, xv_sorted, d_sorted, perm;   // perm: stored slot -> caller's index
     DevBuf block_box;                       // [n_pad / BOXROWS][2 dim]: min, max of every BOXROWS stored points
     int64_t n_pad = 0;
+    bool run_layout = false;                // runs of input points kept whole in the stored order
     std::vector<double> block_dmin;         // host: smallest wall distance of each stored block
     // Control sets of the last finished request (warm start), host copies per level.
     std::vector<std::vector<int64_t>> last_ctrl;

@@ -3,8 +3,8 @@
 //
 //   out_k(p) = base_k(p) - sign * sum_l psi(d_p / D_l) sum_{c in level l} phi(||x_p - x_c|| / R_l) alpha_k,c
 //
-// Design (VALU-bound: about 22 vector slots per point/control pair in 2D, 25 in 3D, against 40-56
-// bytes of HBM traffic per point):
+// Design (VALU-bound: about 22 vector slots per point/control pair in 2D, 25 in 3D, two fewer in
+// the volume sums, against 40-56 bytes of HBM traffic per point):
 //   * points stream as SoA, P points per lane, 256 lanes per workgroup, each wave on 64 P
 //     consecutive stored points;
 //   * the controls of each level are staged through LDS in tiles of 256, scaled by 1/R_l while
@@ -24,7 +24,8 @@
 //     volume stored in spatially compact blocks ordered by their smallest wall distance, or a
 //     stable two-kernel compaction that also writes +0.0 to every dropped point;
 //   * FP64 square root from the hardware reciprocal square-root estimate e refined by one
-//     Goldschmidt step (error ~1.5 e^2) and one Newton correction (error ~1.5 e^3);
+//     Goldschmidt step (error ~1.5 e^2, at most ~37 u): the volume sums stop there; the surface
+//     sums (the greedy's level residuals) add one Newton correction (error ~1.5 e^3);
 //   * mixed precision: the pair arithmetic runs in FP32 on coordinates shifted to a per-workgroup
 //     origin (the workgroup's first point), the basis value is widened and accumulated in FP64.
 #include "basis.h"
@@ -39,15 +40,18 @@ namespace {
 // room for the rounding of the scaled coordinates (FP64, or FP32 on shifted coordinates).
 constexpr double CULL2 = 1.00020001;
 
+// a > 0 normal. y ~ a^-1/2 (1 + e), |e| <= 2^-24.2 (v_rsq_f64); g = a y, h = y / 2. One
+// Goldschmidt step leaves g with relative error ~1.5 e^2 (at most ~37 u, u = 2^-53); with FULL the
+// Newton correction with the unrefined h leaves ~1.5 e^3 (the result to about half an ulp).
+template <bool FULL>
 __device__ __forceinline__ double sqrt_goldschmidt(double a)
 {
-    // a > 0 normal. y ~ a^-1/2 (1 + e); g = a y, h = y / 2. One Goldschmidt step leaves g with
-    // relative error ~1.5 e^2; the Newton correction with the unrefined h leaves ~1.5 e^3.
     double y = __builtin_amdgcn_rsq(a);
     double g = a * y;
     double h = 0.5 * y;
     double r = __builtin_fma(-g, h, 0.5);
     g = __builtin_fma(g, r, g);
+    if constexpr (!FULL) return g;
     double d = __builtin_fma(-g, g, a);
     return __builtin_fma(d, h, g);
 }
@@ -72,8 +76,9 @@ __device__ __forceinline__ void split_range(const SumLevel &L, int s, int S, int
     ce = L.c_begin + (nc * (s + 1)) / S;
 }
 
-// One pair in FP64: phi(|q - c|) for coordinates already scaled by 1/R (Table 1).
-template <int DIM, int BASIS>
+// One pair in FP64: phi(|q - c|) for coordinates already scaled by 1/R (Table 1); the root to
+// half an ulp (FULL) or to the Goldschmidt step's ~37 u.
+template <int DIM, int BASIS, bool FULL>
 __device__ __forceinline__ double pair_f64(const double (&q)[DIM], const double *c)
 {
     double d0 = q[0] - c[0];
@@ -83,7 +88,7 @@ __device__ __forceinline__ double pair_f64(const double (&q)[DIM], const double 
         double dk = q[k] - c[k];
         r2 = __builtin_fma(dk, dk, r2);
     }
-    double eta = sqrt_goldschmidt(r2);
+    double eta = sqrt_goldschmidt<FULL>(r2);
     double t = fmax(1.0 - eta, 0.0);
     return wendland_t<BASIS, double>(eta, t);
 }
@@ -147,20 +152,42 @@ __device__ __forceinline__ void level_accum(const KArgs &a, int l, const double 
         for (int p = 0; p < P; ++p)
 #pragma unroll
             for (int k = 0; k < DIM; ++k) q64[p][k] = xq[p][k] * inv_r;
+        if (a.dwall) {
+            // Volume sums (psi applied): the one-step root, two issue slots fewer per pair.
 #pragma unroll UNR
-        for (int c = c0; c < c1; ++c) {
-            const double *cc = tile + c * ST;
-            double cal[DIM], cpos[DIM];
+            for (int c = c0; c < c1; ++c) {
+                const double *cc = tile + c * ST;
+                double cal[DIM], cpos[DIM];
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) {
-                cal[k] = cc[AOFF + k];
-                cpos[k] = cc[k];
+                for (int k = 0; k < DIM; ++k) {
+                    cal[k] = cc[AOFF + k];
+                    cpos[k] = cc[k];
+                }
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const double ph = pair_f64<DIM, BASIS, false>(q64[p], cpos);
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
+                }
             }
+        } else {
+            // Surface sums (the greedy's level residual, whose rounding can decide the next
+            // level's argmax): the root to half an ulp.
+#pragma unroll UNR
+            for (int c = c0; c < c1; ++c) {
+                const double *cc = tile + c * ST;
+                double cal[DIM], cpos[DIM];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const double ph = pair_f64<DIM, BASIS>(q64[p], cpos);
+                for (int k = 0; k < DIM; ++k) {
+                    cal[k] = cc[AOFF + k];
+                    cpos[k] = cc[k];
+                }
 #pragma unroll
-                for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
+                for (int p = 0; p < P; ++p) {
+                    const double ph = pair_f64<DIM, BASIS, true>(q64[p], cpos);
+#pragma unroll
+                    for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
+                }
             }
         }
     }

@@ -4,7 +4,10 @@
 // wall distance when none is given (distance to the nearest surface point), and stores the volume
 // in blocks of VBLOCK points: the points are put in Z order (a space-filling curve over the
 // bounding box, so each block is spatially compact), cut into blocks, the blocks are stored by
-// increasing smallest wall distance, and the points inside each block by wall distance. The
+// increasing smallest wall distance, and the points inside each block by wall distance. When the
+// input order is spatially local (a structured mesh), runs of ZRUN consecutive input points move
+// as units instead (Z order of the runs, runs inside a block by their smallest wall distance), so
+// that each 64-byte segment of the results is written by one store of one wave. The
 // reduced volume of any request, {d < max D_l} (section 4), is then inside a prefix of whole
 // blocks whose end the host knows from the sorted block minima, with no per-request compaction;
 // every kernel-sum workgroup takes one compact block, which lets it skip the controls whose
@@ -28,6 +31,8 @@ namespace rbf {
 namespace {
 
 constexpr int SORT_BLK = 2048;    // points per workgroup in the radix passes
+constexpr int ZRUN = 8;           // consecutive input points kept together in Z order (64 output bytes)
+static_assert(VBLOCK % ZRUN == 0, "blocks hold whole runs");
 constexpr int NBUCKET = 256;      // 8-bit digits
 
 // d_v = min_s ||x_v - x_s|| over the surface points (surface staged through LDS).
@@ -124,22 +129,114 @@ struct Box {
 };
 
 // Z-order key of every volume point on a 2^16 x 2^16 (2D) or 2^10 x 2^10 x 2^10 (3D) grid over
-// the bounding box; idx = the point's index.
+// the bounding box; idx = the point's index. With runs, the key is taken per run of ZRUN
+// consecutive input points (the key of the run's first point), so that the stable sort keeps each
+// run whole and in order; the last, partial run then takes the largest key (it sorts last and
+// shifts no later run off its alignment).
 template <int DIM>
-__global__ __launch_bounds__(256) void geo_morton(const double *xv, int64_t n, Box box, uint32_t *key,
-                                                  int32_t *idx)
+__global__ __launch_bounds__(256) void geo_morton(const double *xv, int64_t n, Box box, int32_t runs,
+                                                  uint32_t *key, int32_t *idx)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    constexpr double top = DIM == 2 ? 65535.0 : 1023.0;
-    uint32_t q[DIM];
+    const int64_t r = runs ? (i / ZRUN) * ZRUN : i;
+    uint32_t m = 0xffffffffu;
+    if (!runs || r + ZRUN <= n) {
+        constexpr double top = DIM == 2 ? 65535.0 : 1023.0;
+        uint32_t q[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) q[k] = (uint32_t)fmin(top, fmax(0.0, (xv[k * n + i] - box.lo[k]) * box.scale[k]));
-    uint32_t m = 0;
-    if (DIM == 2) m = spread2(q[0]) | (spread2(q[1]) << 1);
-    else m = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[DIM - 1]) << 2);
+        for (int k = 0; k < DIM; ++k)
+            q[k] = (uint32_t)fmin(top, fmax(0.0, (xv[k * n + r] - box.lo[k]) * box.scale[k]));
+        if (DIM == 2) m = spread2(q[0]) | (spread2(q[1]) << 1);
+        else m = spread3(q[0]) | (spread3(q[1]) << 1) | (spread3(q[DIM - 1]) << 2);
+    }
     key[i] = m;
     idx[i] = (int32_t)i;
+}
+
+// Diagonal of the bounding box of every block of VBLOCK points in the point-wise Z order (idx:
+// input index at each sorted position; the last block may be partial). One workgroup per block.
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_blockdiag(const int32_t *idx, const double *xv, int64_t n, double *diag)
+{
+    __shared__ double red[4][2 * DIM];
+    const int64_t b0 = (int64_t)blockIdx.x * VBLOCK;
+    double lo[DIM], hi[DIM];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) {
+        lo[k] = HUGE_VAL;
+        hi[k] = -HUGE_VAL;
+    }
+    for (int j = threadIdx.x; j < VBLOCK && b0 + j < n; j += 256) {
+        const int64_t i = idx[b0 + j];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            lo[k] = fmin(lo[k], xv[k * n + i]);
+            hi[k] = fmax(hi[k], xv[k * n + i]);
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            lo[k] = fmin(lo[k], __shfl_xor(lo[k], off, 64));
+            hi[k] = fmax(hi[k], __shfl_xor(hi[k], off, 64));
+        }
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            red[threadIdx.x >> 6][k] = lo[k];
+            red[threadIdx.x >> 6][DIM + k] = hi[k];
+        }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            const double l = fmin(fmin(red[0][k], red[1][k]), fmin(red[2][k], red[3][k]));
+            const double h = fmax(fmax(red[0][DIM + k], red[1][DIM + k]), fmax(red[2][DIM + k], red[3][DIM + k]));
+            d2 += (h - l) * (h - l);
+        }
+        diag[blockIdx.x] = sqrt(d2);
+    }
+}
+
+// pos[idx[p]] = p: each input point's position in the point-wise Z order.
+__global__ __launch_bounds__(256) void geo_position(const int32_t *idx, int64_t n, int32_t *pos)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) pos[idx[p]] = (int32_t)p;
+}
+
+// Runs of ZRUN consecutive input points that are spatially local: the diagonal of the run's box
+// at most twice that of the point-wise block holding the run's first point. Counted into *local.
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_runlocal(const double *xv, int64_t n, const int32_t *pos,
+                                                    const double *diag, unsigned long long *local)
+{
+    __shared__ int32_t red[4];
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int32_t ok = 0;
+    if ((r + 1) * ZRUN <= n) {
+        double d2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double lo = HUGE_VAL, hi = -HUGE_VAL;
+            for (int j = 0; j < ZRUN; ++j) {
+                const double x = xv[k * n + r * ZRUN + j];
+                lo = fmin(lo, x);
+                hi = fmax(hi, x);
+            }
+            d2 += (hi - lo) * (hi - lo);
+        }
+        const double bd = diag[pos[r * ZRUN] / VBLOCK];
+        ok = d2 <= 4.0 * bd * bd;
+    }
+    for (int off = 32; off > 0; off >>= 1) ok += __shfl_xor(ok, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ok;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicAdd(local, (unsigned long long)(red[0] + red[1] + red[2] + red[3]));
 }
 
 // Per-workgroup digit histograms, stored digit-major: hist[digit * nblk + block].
@@ -245,11 +342,12 @@ __global__ __launch_bounds__(256) void geo_gather(const int32_t *border, const i
     }
 }
 
-// Inside every stored block, order the points by wall distance (ties by slot, so by Z order):
-// a wave then holds points of similar distance, and one whose points all lie at or beyond a
-// level's support distance skips that level. One workgroup per block, bitonic sort in LDS.
+// Point-wise layout: inside every stored block, order the points by wall distance (ties by slot,
+// so by Z order): a wave then holds points of similar distance, and one whose points all lie at
+// or beyond a level's support distance skips that level. One workgroup per block, bitonic sort in
+// LDS.
 template <int DIM>
-__global__ __launch_bounds__(256) void geo_blocksort(int32_t *perm, double *d_sorted, double *x_sorted,
+__global__ __launch_bounds__(256) void geo_pointsort(int32_t *perm, double *d_sorted, double *x_sorted,
                                                      int64_t n_pad)
 {
     static_assert(VBLOCK == 512, "two keys per lane");
@@ -295,6 +393,55 @@ __global__ __launch_bounds__(256) void geo_blocksort(int32_t *perm, double *d_so
         d_sorted[dst] = dv[r];
 #pragma unroll
         for (int k = 0; k < DIM; ++k) x_sorted[k * n_pad + dst] = xvv[r][k];
+    }
+}
+
+// Run layout: inside every stored block, order its runs of ZRUN points by their smallest wall
+// distance (ties by position, so by Z order), each run kept whole and in input order: a wave then
+// holds points of similar distance, and one whose points all lie at or beyond a level's support
+// distance skips that level; its stores cover whole 64-byte segments. One workgroup per block.
+template <int DIM>
+__global__ __launch_bounds__(256) void geo_runsort(int32_t *perm, double *d_sorted, double *x_sorted,
+                                                     int64_t n_pad)
+{
+    static_assert(VBLOCK == 512, "two slots per lane");
+    constexpr int NRUN = VBLOCK / ZRUN;
+    __shared__ double rmin[NRUN];
+    __shared__ int32_t rank[NRUN];
+    const int64_t b0 = (int64_t)blockIdx.x * VBLOCK;
+    const int t = threadIdx.x;
+    if (t < NRUN) {
+        double m = HUGE_VAL;
+        for (int j = 0; j < ZRUN; ++j) m = fmin(m, d_sorted[b0 + t * ZRUN + j]);
+        rmin[t] = m;
+    }
+    __syncthreads();
+    if (t < NRUN) {
+        int r = 0;
+        for (int q = 0; q < NRUN; ++q) r += rmin[q] < rmin[t] || (rmin[q] == rmin[t] && q < t);
+        rank[t] = r;
+    }
+    __syncthreads();
+    int32_t pv[2];
+    double dv[2], xvv[2][DIM];
+    int64_t dst[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int j = t + 256 * r;
+        const int64_t src = b0 + j;
+        dst[r] = b0 + rank[j / ZRUN] * ZRUN + j % ZRUN;
+        pv[r] = perm[src];
+        dv[r] = d_sorted[src];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) xvv[r][k] = x_sorted[k * n_pad + src];
+    }
+    __syncthreads();   // every read of the block is done before any slot is overwritten
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        perm[dst[r]] = pv[r];
+        d_sorted[dst[r]] = dv[r];
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) x_sorted[k * n_pad + dst[r]] = xvv[r][k];
     }
 }
 
@@ -382,23 +529,53 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     RBF_TRY(k1.get(pool, sizeof(uint32_t) * n_v, s));
     RBF_TRY(i0.get(pool, sizeof(int32_t) * n_v, s));
     RBF_TRY(i1.get(pool, sizeof(int32_t) * n_v, s));
-    hipLaunchKernelGGL(geo_morton<DIM>, dim3((unsigned)((n_v + 255) / 256)), dim3(256), 0, s, xv, n_v, box,
-                       k0.as<uint32_t>(), i0.as<int32_t>());
-    // Stable LSD radix sort of (key, index), four 8-bit passes.
     const int64_t nblk = (n_v + SORT_BLK - 1) / SORT_BLK;
     RBF_TRY(hist.get(pool, sizeof(int32_t) * NBUCKET * nblk, s));
-    DevBuf *kin = &k0, *kout = &k1, *iin = &i0, *iout = &i1;
-    for (int shift = 0; shift < 32; shift += 8) {
-        hipLaunchKernelGGL(radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, kin->as<const uint32_t>(), n_v, shift,
-                           hist.as<int32_t>(), nblk);
-        hipLaunchKernelGGL(radix_scan, dim3(1), dim3(1024), 0, s, hist.as<int32_t>(), (int64_t)NBUCKET * nblk);
-        hipLaunchKernelGGL(radix_place, dim3((unsigned)nblk), dim3(256), 0, s, kin->as<const uint32_t>(),
-                           iin->as<const int32_t>(), n_v, shift, hist.as<const int32_t>(), nblk,
-                           kout->as<uint32_t>(), iout->as<int32_t>());
-        std::swap(kin, kout);
-        std::swap(iin, iout);
+    const unsigned gv = (unsigned)((n_v + 255) / 256);
+    // Stable LSD radix sort of (key, index) by Z-order key, four 8-bit passes; the result is back
+    // in k0 / i0.
+    auto zsort = [&](int32_t runs) {
+        hipLaunchKernelGGL(geo_morton<DIM>, dim3(gv), dim3(256), 0, s, xv, n_v, box, runs, k0.as<uint32_t>(),
+                           i0.as<int32_t>());
+        DevBuf *kin = &k0, *kout = &k1, *iin = &i0, *iout = &i1;
+        for (int shift = 0; shift < 32; shift += 8) {
+            hipLaunchKernelGGL(radix_hist, dim3((unsigned)nblk), dim3(256), 0, s, kin->as<const uint32_t>(), n_v,
+                               shift, hist.as<int32_t>(), nblk);
+            hipLaunchKernelGGL(radix_scan, dim3(1), dim3(1024), 0, s, hist.as<int32_t>(), (int64_t)NBUCKET * nblk);
+            hipLaunchKernelGGL(radix_place, dim3((unsigned)nblk), dim3(256), 0, s, kin->as<const uint32_t>(),
+                               iin->as<const int32_t>(), n_v, shift, hist.as<const int32_t>(), nblk,
+                               kout->as<uint32_t>(), iout->as<int32_t>());
+            std::swap(kin, kout);
+            std::swap(iin, iout);
+        }
+    };
+    zsort(0);
+    // Runs of ZRUN consecutive input points are kept whole when the input order is spatially
+    // local (structured meshes): at least 80% of the runs span at most twice the diagonal of the
+    // point-wise block that holds their first point. Then every output line is written by one
+    // wave. Otherwise (scattered input order) the point-wise order stands.
+    bool runs = false;
+    const int64_t n_runs = n_v / ZRUN;
+    if (n_runs >= 64) {
+        DevBuf local, diag;
+        RBF_TRY(local.get(pool, sizeof(unsigned long long), s));
+        RBF_TRY(diag.get(pool, sizeof(double) * nb, s));
+        RBF_HIP(hipMemsetAsync(local.ptr, 0, sizeof(unsigned long long), s));
+        hipLaunchKernelGGL(geo_blockdiag<DIM>, dim3((unsigned)nb), dim3(256), 0, s, i0.as<const int32_t>(), xv, n_v,
+                           diag.as<double>());
+        hipLaunchKernelGGL(geo_position, dim3(gv), dim3(256), 0, s, i0.as<const int32_t>(), n_v, i1.as<int32_t>());
+        hipLaunchKernelGGL(geo_runlocal<DIM>, dim3((unsigned)((n_runs + 255) / 256)), dim3(256), 0, s, xv, n_v,
+                           i1.as<const int32_t>(), diag.as<const double>(), local.as<unsigned long long>());
+        unsigned long long nl = 0;
+        RBF_HIP(hipMemcpyAsync(&nl, local.ptr, sizeof nl, hipMemcpyDeviceToHost, s));
+        RBF_HIP(hipStreamSynchronize(s));
+        settle_all(local, diag);
+        runs = (double)nl >= 0.8 * (double)n_runs;
+        if (runs) zsort(1);
     }
+    g.run_layout = runs;
     RBF_HIP(hipGetLastError());
+    DevBuf *iin = &i0;
     // Blocks of VBLOCK points in Z order, stored by increasing smallest wall distance: the
     // points of any support distance D then lie in a prefix of whole blocks.
     RBF_TRY(bmin.get(pool, sizeof(double) * nb, s));
@@ -417,8 +594,12 @@ rbf_status build_geometry(rbf_ctx ctx, Geometry &g, const double *xs, const doub
     hipLaunchKernelGGL(geo_gather<DIM>, dim3((unsigned)((n_pad + 255) / 256)), dim3(256), 0, s,
                        border.as<const int32_t>(), iin->as<const int32_t>(), d, xv, n_v, n_pad,
                        g.perm.as<int32_t>(), g.d_sorted.as<double>(), g.xv_sorted.as<double>());
-    hipLaunchKernelGGL(geo_blocksort<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<int32_t>(),
-                       g.d_sorted.as<double>(), g.xv_sorted.as<double>(), n_pad);
+    if (runs)
+        hipLaunchKernelGGL(geo_runsort<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<int32_t>(),
+                           g.d_sorted.as<double>(), g.xv_sorted.as<double>(), n_pad);
+    else
+        hipLaunchKernelGGL(geo_pointsort<DIM>, dim3((unsigned)nb), dim3(256), 0, s, g.perm.as<int32_t>(),
+                           g.d_sorted.as<double>(), g.xv_sorted.as<double>(), n_pad);
     RBF_TRY(g.block_box.get(pool, sizeof(double) * 2 * DIM * (n_pad / BOXROWS), s));
     hipLaunchKernelGGL(geo_blockbox<DIM>, dim3((unsigned)(n_pad / 256)), dim3(256), 0, s, g.perm.as<const int32_t>(),
                        g.xv_sorted.as<const double>(), n_pad, g.block_box.as<double>());
@@ -438,9 +619,9 @@ int64_t prefix_for(const Geometry &g, double D)
 
 // Work of each row group of a resident kernel sum (one workgroup per group of `rows` stored
 // rows): the controls the workgroup will keep (those within R_l of the group's box, with the
-// kernel's margin), summed over the levels whose support distance reaches the group (its first row
-// holds its smallest wall distance, rows being sorted by it within each stored block). That is the
-// length of the workgroup's pair loop: its waves run side by side on the compute unit's SIMDs.
+// kernel's margin), summed over the levels whose support distance reaches the group (its smallest
+// wall distance is below D_l). That is the length of the workgroup's pair loop: its waves run
+// side by side on the compute unit's SIMDs.
 struct OrderLevels {
     int32_t n_levels;
     double inv_r[RBF_MAX_LEVELS], D[RBF_MAX_LEVELS];
@@ -453,8 +634,14 @@ __global__ __launch_bounds__(256) void geo_group_weight(const double *xc, int64_
                                                         double *weight)
 {
     __shared__ int32_t red[4][RBF_MAX_LEVELS];
+    __shared__ double dred[4];
     const int64_t r0 = (int64_t)blockIdx.x * rows;
-    const double dmin = d_sorted[r0];
+    double dm = HUGE_VAL;   // the group's smallest wall distance
+    for (int j = threadIdx.x; j < rows; j += 256) dm = fmin(dm, d_sorted[r0 + j]);
+    for (int off = 32; off > 0; off >>= 1) dm = fmin(dm, __shfl_xor(dm, off, 64));
+    if ((threadIdx.x & 63) == 0) dred[threadIdx.x >> 6] = dm;
+    __syncthreads();
+    const double dmin = fmin(fmin(dred[0], dred[1]), fmin(dred[2], dred[3]));
     double lo[DIM], hi[DIM];
 #pragma unroll
     for (int k = 0; k < DIM; ++k) {

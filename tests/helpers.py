@@ -9,7 +9,8 @@ evaluation of it (GPU or oracle), with u = 2^-53:
   * each basis value phi(eta) carries the error of eta. On the GPU the coordinates are scaled by
     1/R before the differences (|d eta| <= u (4 sqrt(dim) rho/R + 5), rho the largest coordinate
     magnitude: two roundings of each scaled coordinate, the difference, the dim-term sum of
-    squares, the refined square root), then |d phi| <= max|phi'| |d eta| + 5 u (the polynomial:
+    squares, the refined square root; the volume sums take the root from one Goldschmidt step, and
+    5 becomes 44.4 there: ROOT_U), then |d phi| <= max|phi'| |d eta| + 5 u (the polynomial:
     max|phi'| = 2 (C0), 2.11 (C2), 2.50 (C4), 2.82 (C6)); the oracle's eta is better. Each value
     multiplies one |alpha_c|, so this enters as eps_phi A, A = sum_l psi_l sum_{eta_lc < 1} |alpha_c|.
   The GPU and the oracle then differ by at most 2 (gamma_n S + eps_phi A). The bound is a worst
@@ -22,6 +23,11 @@ import numpy as np
 U64 = 2.0 ** -53
 U32 = 2.0 ** -24
 MAX_DPHI = {"c0": 2.0, "c2": 2.1094, "c4": 2.4998, "c6": 2.8192}
+# Error of eta's last steps in units of u (eta <= 1 in support): the refined square root of the
+# surface sums (half an ulp) with the difference and the sum of squares, 5 in all; the volume sums
+# (psi applied) stop the root after its Goldschmidt step, relative error 1.5 e^2 with
+# |e| <= 2^-24.2 for v_rsq_f64, i.e. 1.5 * 2^4.6 = 36.4 u, plus the step's own roundings.
+ROOT_U = {False: 5.0, True: 5.0 + 36.4 + 3.0}
 
 
 def to_dev(a):
@@ -43,9 +49,10 @@ class SumMagnitude(float):
     sum_l psi_l sum_{c in support} |alpha_c|, n = the most terms one point sums, rho_r = the largest
     coordinate magnitude over the smallest radius, dim and the basis."""
 
-    def __new__(cls, S, A=0.0, n=1, rho_r=0.0, dim=3, basis="c2"):
+    def __new__(cls, S, A=0.0, n=1, rho_r=0.0, dim=3, basis="c2", volume=False):
         obj = super().__new__(cls, S)
         obj.A, obj.n, obj.rho_r, obj.dim, obj.basis = float(A), int(n), float(rho_r), dim, basis
+        obj.volume = bool(volume)
         return obj
 
 
@@ -79,7 +86,8 @@ def sum_magnitude(orc, radius, level_off, xc, alpha, pts, dwall=None, D=None, ba
     if not used or not live.any():
         return SumMagnitude(0.0)
     rho = max(np.abs(pts[:, live]).max(), np.abs(xc).max() if xc.size else 0.0)
-    return SumMagnitude(S.max(), A.max(), n.max() + 2 * len(radius), rho / min(used), dim, basis)
+    return SumMagnitude(S.max(), A.max(), n.max() + 2 * len(radius), rho / min(used), dim, basis,
+                        volume=dwall is not None)
 
 
 def gamma(n, u=U64):
@@ -91,7 +99,7 @@ def fp64_bound(scale, S):
     plus 1e-10 of the result's scale."""
     if not isinstance(S, SumMagnitude):
         S = SumMagnitude(S)
-    eps_phi = U64 * (MAX_DPHI[S.basis] * (4.0 * math.sqrt(S.dim) * S.rho_r + 5.0) + 5.0)
+    eps_phi = U64 * (MAX_DPHI[S.basis] * (4.0 * math.sqrt(S.dim) * S.rho_r + ROOT_U[S.volume]) + 5.0)
     return 1e-10 * scale + 2.0 * (gamma(S.n) * float(S) + eps_phi * S.A)
 
 
