@@ -193,6 +193,27 @@ void KernelTimers::end(const char *name, hipEvent_t a, hipStream_t s)
     pending.push_back(Pending{name, a, b});
 }
 
+void KernelTimers::pair(hipEvent_t *a, hipEvent_t *b)
+{
+    *a = *b = nullptr;
+    if (!enabled) return;
+    *a = take();
+    *b = take();
+    if (!*a || !*b) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (*a) spare.push_back(*a);
+        if (*b) spare.push_back(*b);
+        *a = *b = nullptr;
+    }
+}
+
+void KernelTimers::add(const char *name, hipEvent_t a, hipEvent_t b)
+{
+    if (!a || !b) return;
+    std::lock_guard<std::mutex> lk(mu);
+    pending.push_back(Pending{name, a, b});
+}
+
 unsigned long long *KernelTimers::counter(const char *name)
 {
     std::lock_guard<std::mutex> lk(mu);

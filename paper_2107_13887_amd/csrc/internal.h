@@ -179,6 +179,10 @@ struct KernelTimers {
     std::map<std::string, int> slot;
     void begin(hipEvent_t *a, hipStream_t s);
     void end(const char *name, hipEvent_t a, hipStream_t s);
+    // Two events for a kernel's own start and end (hipExtLaunchKernel), null while timing is
+    // off; add() files them under name once the launch is enqueued.
+    void pair(hipEvent_t *a, hipEvent_t *b);
+    void add(const char *name, hipEvent_t a, hipEvent_t b);
     void resolve();
     unsigned long long *counter(const char *name);   // null while timing is off
     ~KernelTimers();

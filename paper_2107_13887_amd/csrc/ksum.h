@@ -39,8 +39,11 @@ struct KArgs {
 };
 
 // Enqueue the kernel-sum grid (one workgroup per BLOCK * P rows, gridDim.y splits of the control
-// lists) for the given dimension, points per lane, FP32 pair form and basis.
-void launch_sum(const KArgs &a, dim3 grid, int dim, int P, bool mixed, int32_t basis, hipStream_t s);
+// lists) for the given dimension, points per lane, FP32 pair form and basis. start / stop, when
+// given, receive the kernel's own start and end times (hipExtLaunchKernel), which leave out the
+// host's launch latency that events recorded around the launch on an idle stream would include.
+void launch_sum(const KArgs &a, dim3 grid, int dim, int P, bool mixed, int32_t basis, hipStream_t s,
+                hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // Sum the split partials in split order and write the final values.
 void launch_finalize(const KArgs &a, int dim, int blocks, hipStream_t s);
 // Stable compaction of {v : d_v < dmax} into work[0, *n_work), +0.0 written to every dropped

@@ -28,6 +28,8 @@
 //     sums (the greedy's level residuals) add one Newton correction (error ~1.5 e^3);
 //   * mixed precision: the pair arithmetic runs in FP32 on coordinates shifted to a per-workgroup
 //     origin (the workgroup's first point), the basis value is widened and accumulated in FP64.
+#include <hip/hip_ext.h>
+
 #include "basis.h"
 #include "ksum.h"
 
@@ -577,38 +579,46 @@ __global__ __launch_bounds__(BLOCK) void reduce_scatter(const double *d, int64_t
 }
 
 template <int DIM, int P, int BASIS>
-void launch_sum_t(const KArgs &a, dim3 grid, bool mixed, hipStream_t s)
+void launch_sum_t(const KArgs &a, dim3 grid, bool mixed, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    if (mixed)
+    if (e0) {
+        if (mixed)
+            hipExtLaunchKernelGGL((ksum_kernel<DIM, P, true, BASIS>), grid, dim3(BLOCK), 0, s, e0, e1, 0, a);
+        else
+            hipExtLaunchKernelGGL((ksum_kernel<DIM, P, false, BASIS>), grid, dim3(BLOCK), 0, s, e0, e1, 0, a);
+    } else if (mixed) {
         hipLaunchKernelGGL((ksum_kernel<DIM, P, true, BASIS>), grid, dim3(BLOCK), 0, s, a);
-    else
+    } else {
         hipLaunchKernelGGL((ksum_kernel<DIM, P, false, BASIS>), grid, dim3(BLOCK), 0, s, a);
+    }
 }
 
 template <int DIM, int BASIS>
-void launch_sum_p(const KArgs &a, dim3 grid, int P, bool mixed, hipStream_t s)
+void launch_sum_p(const KArgs &a, dim3 grid, int P, bool mixed, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
 {
-    if (P == 1) launch_sum_t<DIM, 1, BASIS>(a, grid, mixed, s);
-    else launch_sum_t<DIM, 2, BASIS>(a, grid, mixed, s);
+    if (P == 1) launch_sum_t<DIM, 1, BASIS>(a, grid, mixed, s, e0, e1);
+    else launch_sum_t<DIM, 2, BASIS>(a, grid, mixed, s, e0, e1);
 }
 
 template <int DIM>
-void launch_sum_b(const KArgs &a, dim3 grid, int P, bool mixed, int32_t basis, hipStream_t s)
+void launch_sum_b(const KArgs &a, dim3 grid, int P, bool mixed, int32_t basis, hipStream_t s, hipEvent_t e0,
+                  hipEvent_t e1)
 {
     switch (basis) {
-    case RBF_WENDLAND_C0: launch_sum_p<DIM, RBF_WENDLAND_C0>(a, grid, P, mixed, s); break;
-    case RBF_WENDLAND_C4: launch_sum_p<DIM, RBF_WENDLAND_C4>(a, grid, P, mixed, s); break;
-    case RBF_WENDLAND_C6: launch_sum_p<DIM, RBF_WENDLAND_C6>(a, grid, P, mixed, s); break;
-    default: launch_sum_p<DIM, RBF_WENDLAND_C2>(a, grid, P, mixed, s); break;
+    case RBF_WENDLAND_C0: launch_sum_p<DIM, RBF_WENDLAND_C0>(a, grid, P, mixed, s, e0, e1); break;
+    case RBF_WENDLAND_C4: launch_sum_p<DIM, RBF_WENDLAND_C4>(a, grid, P, mixed, s, e0, e1); break;
+    case RBF_WENDLAND_C6: launch_sum_p<DIM, RBF_WENDLAND_C6>(a, grid, P, mixed, s, e0, e1); break;
+    default: launch_sum_p<DIM, RBF_WENDLAND_C2>(a, grid, P, mixed, s, e0, e1); break;
     }
 }
 
 }  // namespace
 
-void launch_sum(const KArgs &a, dim3 grid, int dim, int P, bool mixed, int32_t basis, hipStream_t s)
+void launch_sum(const KArgs &a, dim3 grid, int dim, int P, bool mixed, int32_t basis, hipStream_t s,
+                hipEvent_t start, hipEvent_t stop)
 {
-    if (dim == 2) launch_sum_b<2>(a, grid, P, mixed, basis, s);
-    else launch_sum_b<3>(a, grid, P, mixed, basis, s);
+    if (dim == 2) launch_sum_b<2>(a, grid, P, mixed, basis, s, start, stop);
+    else launch_sum_b<3>(a, grid, P, mixed, basis, s, start, stop);
 }
 
 void launch_finalize(const KArgs &a, int dim, int blocks, hipStream_t s)

@@ -147,11 +147,11 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s, cons
     const char *name = pb.dwall ? (mixed ? "volume_ksum_mixed" : "volume_ksum_fp64")
                                 : (mixed ? "surface_ksum_mixed" : "surface_ksum_fp64");
     a.pairs = ext ? nullptr : ctx->timers.counter(name);
-    hipEvent_t t0 = nullptr;
-    if (!ext) ctx->timers.begin(&t0, s);
-    launch_sum(a, grid, DIM, P, mixed, pb.basis, s);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (!ext) ctx->timers.pair(&t0, &t1);
+    launch_sum(a, grid, DIM, P, mixed, pb.basis, s, t0, t1);
     RBF_HIP(hipGetLastError());
-    if (!ext) ctx->timers.end(name, t0, s);
+    ctx->timers.add(name, t0, t1);
     if (S > 1) {
         const int gf = (int)std::min<int64_t>((n_rows + BLOCK - 1) / BLOCK, 8192);
         launch_finalize(a, DIM, gf, s);
