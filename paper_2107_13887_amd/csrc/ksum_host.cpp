@@ -104,6 +104,10 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s, cons
         }
         launch_reduce(pb.dwall, pb.n_p, dmax, cn, nw, wk, pb.out, DIM, s);
         RBF_HIP(hipGetLastError());
+        // RBF_KSUM_FAIL_AFTER_COMPACTION=1 fails the call here, with its compaction kernels
+        // enqueued (tests: its buffers must stay reserved until its stream has passed them).
+        if (const char *e = getenv("RBF_KSUM_FAIL_AFTER_COMPACTION"); e && atoi(e) && !ext)
+            return fail(RBF_E_NOMEM, "failure forced after the compaction (RBF_KSUM_FAIL_AFTER_COMPACTION)");
         a.work = wk;
         a.n_work_dev = nw;
     }

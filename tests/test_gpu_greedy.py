@@ -2,9 +2,10 @@
 
 Bar: the control points of every level identical to the oracle's (same indices, same order);
 the final surface residual and the volume update built from the GPU's control set within
-1e-10 of the result's scale plus 64 u S, S the magnitude of the summed terms (the rounding floor
-of any FP64 evaluation of these sums); the weights themselves within 1e-6 normwise (they carry the condition
-number of Phi_cc, which the interpolant values do not).
+1e-10 of the result's scale plus the stated forward-error bound of two FP64 evaluations of these
+sums (tests/helpers.py: 2 (gamma_n S + eps_phi A), S the magnitude of the summed terms); the
+weights themselves within 1e-6 normwise (they carry the condition number of Phi_cc, which the
+interpolant values do not).
 """
 import numpy as np
 import pytest

@@ -1,10 +1,14 @@
 """GPU parity of the volume update (eqs. (19), (23)) and the interpolant evaluation (eq. (1))
 against the FP64 oracle, through the C ABI.
 
-Tolerances: FP64 path max_v ||dv_gpu - dv_oracle|| <= 1e-10 max_v ||dv_oracle|| + 64 u S, where
-S = max_v sum_l psi sum_c phi |alpha_c| is the magnitude of the summed terms (two correct FP64
-evaluations differ by about u S; with wide supports S exceeds |dv| by up to 1e8); mixed path (FP32 pair arithmetic, FP64 accumulation) 1e-5 of the scale plus 16 u32 S, u32 = 2^-24:
-each FP32 basis value carries a few u32 of error, so the sum carries about u32 S. Points at or beyond every support distance D_l must be +0.0 bit for bit.
+Tolerances (tests/helpers.py): the FP64 path within 1e-10 of the result's scale plus the stated
+forward-error bound 2 (gamma_n S + eps_phi A) of two FP64 evaluations of the same sums (S the
+magnitude of the summed terms, A that of the weights in support, eps_phi the basis value's own
+error, with the one-step root of the volume sums); the measured difference is printed in units
+of u S. The mixed path (FP32 pair arithmetic, FP64 accumulation) is held to the same form with
+u32 = 2^-24 for the pair part (mixed_bound). Points at or beyond every support distance D_l must
+be +0.0 bit for bit. A call that fails after its compaction kernels are enqueued keeps its buffers
+reserved until its stream has passed them.
 """
 import numpy as np
 import pytest
@@ -152,3 +156,37 @@ def test_binding_uses_the_current_stream():
     with torch.cuda.stream(s):
         assert rbfdef._stream(None) == s.cuda_stream == torch.cuda.current_stream().cuda_stream
     assert rbfdef._stream(s) == s.cuda_stream
+
+
+def test_failed_call_keeps_its_buffers_until_its_kernels_end(gctx):
+    """A plain volume update that fails (forced: RBF_KSUM_FAIL_AFTER_COMPACTION) after its
+    compaction kernels are enqueued returns RBF_E_NOMEM and hands its buffers back to the pool only
+    once its stream has passed them. A call of the same sizes issued right after it on another
+    stream, which would otherwise be given those blocks while the failed call's kernels still write
+    them, returns the same bits as alone."""
+    rng = np.random.default_rng(11)
+    n_v, n_c = 3_000_000, 600
+    xv = torch.from_numpy(rng.uniform(-1.0, 1.0, (3, n_v))).to("cuda:0")
+    dwall = torch.from_numpy(rng.uniform(0.0, 1.0, n_v)).to("cuda:0")
+    xc = torch.from_numpy(rng.uniform(-1.0, 1.0, (3, n_c))).to("cuda:0")
+    al = torch.from_numpy(rng.uniform(-1e-3, 1e-3, (3, n_c))).to("cuda:0")
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    dv_a = torch.empty((3, n_v), dtype=torch.float64, device="cuda:0")   # alive until the end: the
+    # failed call's compaction still writes its zeros there after the call has returned
+    call = lambda D, st, dv=None: rbfdef.rbf_volume_update(gctx, [0.3], [D], [0, n_c], xc, al, xv, dwall, dv=dv,
+                                                           stream=st)
+    ref = call(0.6, sb)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        print(f"case failed call then another, repetition {rep}", flush=True)
+        import os
+        os.environ["RBF_KSUM_FAIL_AFTER_COMPACTION"] = "1"
+        try:
+            with pytest.raises(rbfdef.RbfError) as e:
+                call(0.2, sa, dv_a)
+        finally:
+            del os.environ["RBF_KSUM_FAIL_AFTER_COMPACTION"]
+        assert e.value.status == rbfdef.RBF_E_NOMEM
+        got = call(0.6, sb)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
