@@ -28,6 +28,28 @@ __device__ __forceinline__ T wendland_t(T eta, T t)
     }
 }
 
+// The same functions written in t alone (eta = 1 - t), for a caller that forms t without eta:
+// tc = max(t, 0) carries the compact support and t (unclamped) the polynomial factor:
+//   C0: tc^2,  C2: tc^4 (5 - 4 t),  C4: tc^6 (35/3 t^2 - 88/3 t + 56/3),
+//   C6: tc^8 (-32 t^3 + 121 t^2 - 154 t + 66).
+template <int BASIS, typename T>
+__device__ __forceinline__ T wendland_tform(T tc, T t)
+{
+    const T t2 = tc * tc;
+    if constexpr (BASIS == RBF_WENDLAND_C0) {
+        return t2;
+    } else if constexpr (BASIS == RBF_WENDLAND_C2) {
+        return (t2 * t2) * __builtin_fma(T(-4), t, T(5));
+    } else if constexpr (BASIS == RBF_WENDLAND_C4) {
+        const T t4 = t2 * t2;
+        return (t4 * t2) * __builtin_fma(__builtin_fma(T(35.0 / 3.0), t, T(-88.0 / 3.0)), t, T(56.0 / 3.0));
+    } else {
+        const T t4 = t2 * t2;
+        return (t4 * t4) *
+               __builtin_fma(__builtin_fma(__builtin_fma(T(-32), t, T(121)), t, T(-154)), t, T(66));
+    }
+}
+
 // Runtime selection (uniform across a launch), FP64.
 __device__ __forceinline__ double wendland(int32_t basis, double eta)
 {

@@ -3,8 +3,8 @@
 //
 //   out_k(p) = base_k(p) - sign * sum_l psi(d_p / D_l) sum_{c in level l} phi(||x_p - x_c|| / R_l) alpha_k,c
 //
-// Design (VALU-bound: about 22 vector slots per point/control pair in 2D, 25 in 3D, two fewer in
-// the volume sums, against 40-56 bytes of HBM traffic per point):
+// Design (VALU-bound: about 22 vector slots per point/control pair in 2D, 25 in 3D, three fewer
+// in the volume sums, against 40-56 bytes of HBM traffic per point):
 //   * points stream as SoA, P points per lane, 256 lanes per workgroup, each wave on 64 P
 //     consecutive stored points;
 //   * the controls of each level are staged through LDS in tiles of 256, scaled by 1/R_l while
@@ -24,8 +24,9 @@
 //     volume stored in spatially compact blocks ordered by their smallest wall distance, or a
 //     stable two-kernel compaction that also writes +0.0 to every dropped point;
 //   * FP64 square root from the hardware reciprocal square-root estimate e refined by one
-//     Goldschmidt step (error ~1.5 e^2, at most ~37 u): the volume sums stop there; the surface
-//     sums (the greedy's level residuals) add one Newton correction (error ~1.5 e^3);
+//     Goldschmidt step (error ~1.5 e^2, at most ~37 u): the volume sums stop there and form
+//     t = 1 - eta directly from it (coordinates scaled by 2 / R, the polynomial in t); the
+//     surface sums (the greedy's level residuals) add one Newton correction (error ~1.5 e^3);
 //   * mixed precision: the pair arithmetic runs in FP32 on coordinates shifted to a per-workgroup
 //     origin (the workgroup's first point), the basis value is widened and accumulated in FP64.
 #include <hip/hip_ext.h>
@@ -43,9 +44,8 @@ namespace {
 constexpr double CULL2 = 1.00020001;
 
 // a > 0 normal. y ~ a^-1/2 (1 + e), |e| <= 2^-24.2 (v_rsq_f64); g = a y, h = y / 2. One
-// Goldschmidt step leaves g with relative error ~1.5 e^2 (at most ~37 u, u = 2^-53); with FULL the
-// Newton correction with the unrefined h leaves ~1.5 e^3 (the result to about half an ulp).
-template <bool FULL>
+// Goldschmidt step leaves g with relative error ~1.5 e^2 (at most ~37 u, u = 2^-53); the Newton
+// correction with the unrefined h leaves ~1.5 e^3 (the result to about half an ulp).
 __device__ __forceinline__ double sqrt_goldschmidt(double a)
 {
     double y = __builtin_amdgcn_rsq(a);
@@ -53,7 +53,6 @@ __device__ __forceinline__ double sqrt_goldschmidt(double a)
     double h = 0.5 * y;
     double r = __builtin_fma(-g, h, 0.5);
     g = __builtin_fma(g, r, g);
-    if constexpr (!FULL) return g;
     double d = __builtin_fma(-g, g, a);
     return __builtin_fma(d, h, g);
 }
@@ -78,9 +77,9 @@ __device__ __forceinline__ void split_range(const SumLevel &L, int s, int S, int
     ce = L.c_begin + (nc * (s + 1)) / S;
 }
 
-// One pair in FP64: phi(|q - c|) for coordinates already scaled by 1/R (Table 1); the root to
-// half an ulp (FULL) or to the Goldschmidt step's ~37 u.
-template <int DIM, int BASIS, bool FULL>
+// One pair in FP64: phi(|q - c|) for coordinates already scaled by 1/R (Table 1), the root to
+// half an ulp.
+template <int DIM, int BASIS>
 __device__ __forceinline__ double pair_f64(const double (&q)[DIM], const double *c)
 {
     double d0 = q[0] - c[0];
@@ -90,9 +89,30 @@ __device__ __forceinline__ double pair_f64(const double (&q)[DIM], const double 
         double dk = q[k] - c[k];
         r2 = __builtin_fma(dk, dk, r2);
     }
-    double eta = sqrt_goldschmidt<FULL>(r2);
+    double eta = sqrt_goldschmidt(r2);
     double t = fmax(1.0 - eta, 0.0);
     return wendland_t<BASIS, double>(eta, t);
+}
+
+// The volume sums' pair, on coordinates scaled by 2 / R: s = 4 eta^2 (+1e-200), y = rsq(s),
+// G = s y = 2 eta (1 + e) and r = 1 - G y. One Goldschmidt step gives eta = G / 2 + G r / 4
+// (relative error ~1.5 e^2, the first step of sqrt_goldschmidt), so t = 1 - eta = 1 + G (-1/2 - r / 4)
+// comes out directly and the polynomial is taken in t: one issue slot fewer than forming eta.
+template <int DIM, int BASIS>
+__device__ __forceinline__ double pair_f64_t(const double (&q)[DIM], const double *c)
+{
+    double d0 = q[0] - c[0];
+    double s = __builtin_fma(d0, d0, 1e-200);
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) {
+        double dk = q[k] - c[k];
+        s = __builtin_fma(dk, dk, s);
+    }
+    const double y = __builtin_amdgcn_rsq(s);
+    const double G = s * y;
+    const double r = __builtin_fma(-G, y, 1.0);
+    const double t = __builtin_fma(G, __builtin_fma(r, -0.25, -0.5), 1.0);
+    return wendland_tform<BASIS, double>(fmax(t, 0.0), t);
 }
 
 template <int DIM, int BASIS>
@@ -149,13 +169,16 @@ __device__ __forceinline__ void level_accum(const KArgs &a, int l, const double 
             }
         }
     } else {
+        // Volume sums (psi applied) take coordinates scaled by 2 / R (pair_f64_t, the staged
+        // controls likewise), surface sums by 1 / R.
+        const double sc = a.dwall ? 2.0 * inv_r : inv_r;
         double q64[P][DIM];
 #pragma unroll
         for (int p = 0; p < P; ++p)
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) q64[p][k] = xq[p][k] * inv_r;
+            for (int k = 0; k < DIM; ++k) q64[p][k] = xq[p][k] * sc;
         if (a.dwall) {
-            // Volume sums (psi applied): the one-step root, two issue slots fewer per pair.
+            // Volume sums: the one-step root with t formed directly (pair_f64_t).
 #pragma unroll UNR
             for (int c = c0; c < c1; ++c) {
                 const double *cc = tile + c * ST;
@@ -167,7 +190,7 @@ __device__ __forceinline__ void level_accum(const KArgs &a, int l, const double 
                 }
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    const double ph = pair_f64<DIM, BASIS, false>(q64[p], cpos);
+                    const double ph = pair_f64_t<DIM, BASIS>(q64[p], cpos);
 #pragma unroll
                     for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
                 }
@@ -186,7 +209,7 @@ __device__ __forceinline__ void level_accum(const KArgs &a, int l, const double 
                 }
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
-                    const double ph = pair_f64<DIM, BASIS, true>(q64[p], cpos);
+                    const double ph = pair_f64<DIM, BASIS>(q64[p], cpos);
 #pragma unroll
                     for (int k = 0; k < DIM; ++k) la[p][k] = __builtin_fma(ph, cal[k], la[p][k]);
                 }
@@ -465,7 +488,7 @@ __global__ __launch_bounds__(BLOCK) void ksum_kernel(KArgs a)
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) {
                     if (f32) reinterpret_cast<float *>(dst)[k] = (float)((xck[k] - origin[k]) * inv_r);
-                    else dst[k] = xck[k] * inv_r;
+                    else dst[k] = xck[k] * (a.dwall ? 2.0 * inv_r : inv_r);
                 }
 #pragma unroll
                 for (int k = 0; k < DIM; ++k) dst[AOFF + k] = ack[k];
