@@ -155,7 +155,11 @@ typedef struct {
  * unselected point of largest ||E_i|| (lowest index on exact ties) until max ||E|| is below the
  * level target; then dS_{l+1} = E. The GPU keeps the Newton basis of the control set at every
  * surface point (the Cholesky factor of Phi_cc bordered by one row per added point), so each
- * iteration costs one rank-one update and one argmax, with no triangular solve.
+ * iteration costs one rank-one update and one argmax, with no triangular solve. A level given
+ * 32 seeds or more (with no resident basis of them, as in a warm start after the basis was
+ * dropped) forms that basis at once: the blocked FP64 Cholesky of the seeds' Phi_cc (eq. (9)) and
+ * blocked triangular solves for the basis at every surface point, on the matrix cores; seeds at
+ * coincident coordinates are appended one by one instead and stop the level at the breakdown.
  * xs, ds: device [dim][n_s] FP64. Blocking. Returns RBF_W_CAP / RBF_W_BREAKDOWN as warnings. */
 rbf_status rbf_greedy_select(rbf_ctx ctx, const rbf_greedy_params *params, int64_t n_s,
                              const double *xs, const double *ds, rbf_ctrl_set *out, void *stream);
