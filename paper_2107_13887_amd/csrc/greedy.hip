@@ -19,8 +19,11 @@
 // extraction, pivot) and an update phase (all workgroups, 64 surface points per tile: new column,
 // error update, tile argmax). On small surfaces a level runs as one persistent cooperative kernel
 // in which every workgroup runs the select phase itself after the iteration's one grid barrier,
-// keeping the Newton row in LDS for its update; on large surfaces (or when a cooperative launch is
-// impossible) the two phases run as two kernel launches per iteration.
+// keeping the Newton row in LDS for its update. When the device holds a workgroup per tile and no
+// other persistent kernel runs, the resident form also keeps each tile's first Newton columns in
+// LDS and its error in registers, and passes what workgroups read from each other through
+// coherent accesses, so that its barrier needs no cache maintenance. On large surfaces (or when a
+// cooperative launch is impossible) the two phases run as two kernel launches per iteration.
 // Reductions run in a fixed order; squared norms are formed without fused multiply-adds so they
 // equal the textbook formula term by term.
 //
@@ -51,6 +54,7 @@ constexpr int UWAVES = 4;     // waves per workgroup, each a slice of the dot pr
 constexpr int NT = UPB * UWAVES;
 constexpr int LCHUNK = 2048;  // Newton row entries staged per LDS pass
 constexpr int64_t LEAN_MAX_TILES = 256;   // largest surface (in tiles) run by the persistent kernel
+constexpr int RES_COLS = 192;             // Newton columns a resident persistent workgroup keeps in LDS
 constexpr int64_t SEED_FACTOR_MIN = 32;   // fewest seeds of a level started from the blocked factor
 
 struct GState {
@@ -103,7 +107,7 @@ struct SelShared {
     double red[UWAVES];
     int32_t stop, skip;
     int64_t n, p;
-    double m2, d, c[3];
+    double m2, d, c[3], xp[3];
 };
 
 struct UpdShared {
@@ -141,6 +145,41 @@ __device__ __forceinline__ double phi_pair(const double *xs, int64_t ld, int64_t
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
             double d = xs[k * ld + i] - xs[k * ld + j];
+            s = s + d * d;
+        }
+    }
+    double eta = sqrt(s) / R;
+    if (eta >= 1.0) return 0.0;
+    return wendland(basis, eta);
+}
+
+// Agent-scope relaxed accesses (global_load / global_store with sc1): coherent across the XCDs'
+// L2 caches for the location itself, with no cache write-back or invalidation. The resident
+// persistent form passes everything one workgroup reads from another (the tile maxima, the error
+// at the selected row, the Newton columns) through these, so its barrier needs no release or
+// acquire fence.
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void st_coh(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// phi_pair on coordinates already at hand, with the same arithmetic.
+template <int DIM>
+__device__ __forceinline__ double phi_xy(const double (&x)[DIM], const double (&y)[DIM], double R, int32_t basis)
+{
+    double s = 0.0;
+    {
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            double d = x[k] - y[k];
             s = s + d * d;
         }
     }
@@ -489,50 +528,70 @@ struct GridBar {
 // short, which makes the failure path testable).
 constexpr unsigned long long LEAN_SPIN_LIMIT = 1ull << 22;
 
+// V(i, jb .. je) . l(jb .. je) for one wave's slice of a tile's columns (V(i, jb) at col[0], the
+// next column UPB doubles on): 16 loads in flight, four partial sums in a fixed order.
+__device__ __forceinline__ double slice_dot(const double *col, const double *l, int jb, int je)
+{
+    int j = jb;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (; j + 16 <= je; j += 16, col += 16 * UPB) {
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = col[q * UPB];
+#pragma unroll
+        for (int q = 0; q < 16; q += 4) {
+            s0 = __builtin_fma(v[q], l[j + q], s0);
+            s1 = __builtin_fma(v[q + 1], l[j + q + 1], s1);
+            s2 = __builtin_fma(v[q + 2], l[j + q + 2], s2);
+            s3 = __builtin_fma(v[q + 3], l[j + q + 3], s3);
+        }
+    }
+    for (; j + 4 <= je; j += 4, col += 4 * UPB) {
+        s0 = __builtin_fma(col[0], l[j], s0);
+        s1 = __builtin_fma(col[UPB], l[j + 1], s1);
+        s2 = __builtin_fma(col[2 * UPB], l[j + 2], s2);
+        s3 = __builtin_fma(col[3 * UPB], l[j + 3], s3);
+    }
+    for (; j < je; ++j, col += UPB) s0 = __builtin_fma(col[0], l[j], s0);
+    return (s0 + s1) + (s2 + s3);
+}
+
+// What a resident workgroup keeps of its tile's row in each lane between iterations: the error as
+// it last wrote it, the coordinates, and whether the row was selected in this level (or lies past
+// the surface). With its first RES_COLS Newton columns in LDS, an update reads no global memory.
 template <int DIM>
+struct ResRow {
+    double e[DIM];
+    double x[DIM];
+    bool sel;
+};
+
+template <int DIM, bool RES>
 __device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_t p, double d,
-                                 const double (&c)[DIM], bool row_in_lds, const double *Ein, double *Eout,
-                                 Cand *part_out, UpdShared &u)
+                                 const double (&c)[DIM], const double (&xp)[DIM], bool row_in_lds,
+                                 const double *Ein, double *Eout, Cand *part_out, UpdShared &u, double *vres,
+                                 ResRow<DIM> &rr)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i = tile * UPB + lane;
     const bool ok = i < a.n_s;
     const double *vt = a.V + tile * a.ldt * UPB + lane;
     const double *prow = a.V + (p / UPB) * a.ldt * UPB + (p % UPB);   // V(p, j) at prow[j UPB]
+    const bool lds = RES && n <= RES_COLS;                               // every column in LDS
 
     double s = 0.0;
     for (int64_t j0 = 0; j0 < n; j0 += LCHUNK) {
         const int nj = (int)min<int64_t>(LCHUNK, n - j0);
         if (!row_in_lds) {
             __syncthreads();
-            for (int t = threadIdx.x; t < nj; t += NT) u.lsh[t] = prow[(j0 + t) * UPB];
+            for (int t = threadIdx.x; t < nj; t += NT)
+                u.lsh[t] = RES ? ld_coh(&prow[(j0 + t) * UPB]) : prow[(j0 + t) * UPB];
             __syncthreads();
         }
         const int per = (nj + UWAVES - 1) / UWAVES;
         const int jb = w * per, je = min(nj, jb + per);
-        const double *col = vt + (j0 + jb) * UPB;
-        int j = jb;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (; j + 16 <= je; j += 16, col += 16 * UPB) {
-            double v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) v[q] = col[q * UPB];
-#pragma unroll
-            for (int q = 0; q < 16; q += 4) {
-                s0 = __builtin_fma(v[q], u.lsh[j + q], s0);
-                s1 = __builtin_fma(v[q + 1], u.lsh[j + q + 1], s1);
-                s2 = __builtin_fma(v[q + 2], u.lsh[j + q + 2], s2);
-                s3 = __builtin_fma(v[q + 3], u.lsh[j + q + 3], s3);
-            }
-        }
-        for (; j + 4 <= je; j += 4, col += 4 * UPB) {
-            s0 = __builtin_fma(col[0], u.lsh[j], s0);
-            s1 = __builtin_fma(col[UPB], u.lsh[j + 1], s1);
-            s2 = __builtin_fma(col[2 * UPB], u.lsh[j + 2], s2);
-            s3 = __builtin_fma(col[3 * UPB], u.lsh[j + 3], s3);
-        }
-        for (; j < je; ++j, col += UPB) s0 = __builtin_fma(col[0], u.lsh[j], s0);
-        s += (s0 + s1) + (s2 + s3);
+        if (lds) s += slice_dot(vres + jb * UPB + lane, u.lsh, jb, je);
+        else s += slice_dot(vt + (j0 + jb) * UPB, u.lsh, jb, je);
     }
     __syncthreads();                                    // psum of the previous tile has been read
     u.psum[w][lane] = s;
@@ -540,19 +599,28 @@ __device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_
     if (w == 0) {
         double m2 = -1.0;
         int64_t idx = -1;
+        if (RES) rr.sel = rr.sel || i == p;
         if (ok) {
             double dot = u.psum[0][lane];
 #pragma unroll
             for (int k = 1; k < UWAVES; ++k) dot += u.psum[k][lane];
-            const double v = (phi_pair<DIM>(a.xs, a.n_s, i, p, a.R, a.basis) - dot) / d;
-            a.V[(tile * a.ldt + n) * UPB + lane] = v;
+            const double ph = RES ? phi_xy<DIM>(rr.x, xp, a.R, a.basis) : phi_pair<DIM>(a.xs, a.n_s, i, p, a.R, a.basis);
+            const double v = (ph - dot) / d;
+            if (RES) st_coh(&a.V[(tile * a.ldt + n) * UPB + lane], v);
+            else a.V[(tile * a.ldt + n) * UPB + lane] = v;
+            if (RES && n < RES_COLS) vres[n * UPB + lane] = v;
             double e[DIM];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
-                e[k] = __builtin_fma(-c[k], v, Ein[k * a.n_s + i]);
-                Eout[k * a.n_s + i] = e[k];
+                e[k] = __builtin_fma(-c[k], v, RES ? rr.e[k] : Ein[k * a.n_s + i]);
+                if (RES) {
+                    st_coh(&Eout[k * a.n_s + i], e[k]);
+                    rr.e[k] = e[k];
+                } else {
+                    Eout[k * a.n_s + i] = e[k];
+                }
             }
-            if (i != p && !a.sel[i]) {
+            if (RES ? !rr.sel : (i != p && !a.sel[i])) {
 #pragma clang fp contract(off)
                 double q = e[0] * e[0];
 #pragma unroll
@@ -562,7 +630,14 @@ __device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_
             }
         }
         wave_argmax(m2, idx);
-        if (lane == 0) part_out[tile] = Cand{m2, idx};
+        if (lane == 0) {
+            if (RES) {
+                st_coh(&part_out[tile].m2, m2);
+                st_coh(&part_out[tile].idx, idx);
+            } else {
+                part_out[tile] = Cand{m2, idx};
+            }
+        }
     }
 }
 
@@ -570,10 +645,10 @@ __device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_
 // barrier: the next point (argmax of the per-tile maxima, or a forced seed), the stop tests, the
 // Newton row l = V[p, 0:n] (kept in LDS for the update when it fits), the pivot and the Newton
 // coefficients. Workgroup 0 writes the outputs. Returns false when the level stops.
-template <int DIM>
+template <int DIM, bool RES>
 __device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double target2, int64_t &n_iter,
                             const double *Ecur, const Cand *part, SelShared &s, UpdShared &u,
-                            int64_t &p_out, double &d_out, double (&c_out)[DIM])
+                            int64_t &p_out, double &d_out, double (&c_out)[DIM], double (&xp_out)[DIM])
 {
     GState *st = a.st;
     const bool writer = blockIdx.x == 0;
@@ -582,7 +657,7 @@ __device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double ta
         double bm = -1.0;
         int64_t bi = -1;
         for (int64_t b = threadIdx.x; b < a.g; b += NT) {
-            const Cand c = part[b];
+            const Cand c = RES ? Cand{ld_coh(&part[b].m2), ld_coh(&part[b].idx)} : part[b];
             if (better(c.m2, c.idx, bm, bi)) {
                 bm = c.m2;
                 bi = c.idx;
@@ -626,14 +701,17 @@ __device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double ta
     }
     const int64_t p = s.p;
     double *row = a.Lpack + (n * (n + 1)) / 2;
-    double ep[DIM];
+    double ep[DIM], xp[DIM];
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int k = 0; k < DIM; ++k) ep[k] = Ecur[k * a.n_s + p];
+        for (int k = 0; k < DIM; ++k) {
+            ep[k] = RES ? ld_coh(&Ecur[k * a.n_s + p]) : Ecur[k * a.n_s + p];
+            xp[k] = a.xs[k * a.n_s + p];
+        }
     const double *prow = a.V + (p / UPB) * a.ldt * UPB + (p % UPB);
     double part_ll = 0.0;
     for (int64_t j = threadIdx.x; j < n; j += NT) {
-        const double v = prow[j * UPB];
+        const double v = RES ? ld_coh(&prow[j * UPB]) : prow[j * UPB];
         if (j < LCHUNK) u.lsh[j] = v;
         if (writer) row[j] = v;
         part_ll = __builtin_fma(v, v, part_ll);
@@ -659,7 +737,10 @@ __device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double ta
             const double d = sqrt(d2);
             s.d = d;
 #pragma unroll
-            for (int k = 0; k < DIM; ++k) s.c[k] = ep[k] / d;
+            for (int k = 0; k < DIM; ++k) {
+                s.c[k] = ep[k] / d;
+                s.xp[k] = xp[k];
+            }
             if (writer) {
                 row[n] = d;
                 st->p = p;
@@ -686,16 +767,21 @@ __device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double ta
     p_out = p;
     d_out = s.d;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) c_out[k] = s.c[k];
+    for (int k = 0; k < DIM; ++k) {
+        c_out[k] = s.c[k];
+        xp_out[k] = s.xp[k];
+    }
     return true;
 }
 
-template <int DIM>
+// RES: one tile per workgroup (the grid has a.g workgroups), resident as ResRow describes.
+template <int DIM, bool RES>
 __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
 {
     __shared__ SelShared s;
     __shared__ UpdShared u;
     __shared__ int32_t abort_sh;
+    __shared__ double vres[RES ? RES_COLS * UPB : 1];   // V(tile, j) for j < RES_COLS, column-major
     const unsigned int nb = gridDim.x;
     // Level state, read before this workgroup's first arrival: workgroup 0 writes it only after
     // every workgroup has arrived.
@@ -704,24 +790,54 @@ __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
     const double target2 = a.st->target2;
     bool pending = false;
     int64_t p = -1;
-    double d = 1.0, c[DIM];
+    double d = 1.0, c[DIM], xp[DIM];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) c[k] = 0.0;
+    for (int k = 0; k < DIM; ++k) c[k] = xp[k] = 0.0;
     double *Eb[2] = {a.E, a.E2};
     Cand *Pb[2] = {a.part, a.part2};
+    ResRow<DIM> rr;
+    if constexpr (RES) {
+        // The level's first error (in a.E), this tile's rows and existing columns; the barrier
+        // below orders these LDS writes before any read.
+        const int64_t i = (int64_t)blockIdx.x * UPB + (threadIdx.x & 63);
+        const bool ok = i < a.n_s;
+#pragma unroll
+        for (int k = 0; k < DIM; ++k) {
+            rr.e[k] = ok ? a.E[k * a.n_s + i] : 0.0;
+            rr.x[k] = ok ? a.xs[k * a.n_s + i] : 0.0;
+        }
+        rr.sel = !ok || a.sel[i] != 0;
+        const double *vt = a.V + (int64_t)blockIdx.x * a.ldt * UPB;
+        const int64_t nf = min<int64_t>(n, RES_COLS) * UPB;
+        for (int64_t t = threadIdx.x; t < nf; t += NT) vres[t] = vt[t];
+    }
     for (int64_t it = 0; it < a.max_iter; ++it) {
         const int par = (int)(it & 1);
         if (pending) {
             const bool row_in_lds = n <= LCHUNK;
-            for (int64_t t = blockIdx.x; t < a.g; t += nb)
-                update_tile_lean<DIM>(a, t, n, p, d, c, row_in_lds, Eb[par ^ 1], Eb[par], Pb[par], u);
+            if constexpr (RES)
+                update_tile_lean<DIM, true>(a, blockIdx.x, n, p, d, c, xp, row_in_lds, Eb[par ^ 1], Eb[par],
+                                            Pb[par], u, vres, rr);
+            else
+                for (int64_t t = blockIdx.x; t < a.g; t += nb)
+                    update_tile_lean<DIM, false>(a, t, n, p, d, c, xp, row_in_lds, Eb[par ^ 1], Eb[par], Pb[par],
+                                                 u, vres, rr);
             n += 1;
             pending = false;
         }
         // Grid barrier: one release per arrival, relaxed polls of the arrival count, one acquire.
+        // The resident form's cross-workgroup data all moves by coherent accesses (ld_coh /
+        // st_coh, issued by wave 0 in the update), so its arrival only waits for those stores to
+        // complete and its departure needs no invalidation.
         __syncthreads();
         if (threadIdx.x == 0) {
-            __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if constexpr (RES) {
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_s_waitcnt(0);
+                __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
             const unsigned int target = nb * (unsigned int)(it + 1);
             unsigned long long spins = 0;
             int32_t ab = 0;
@@ -732,14 +848,15 @@ __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if constexpr (RES) __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             abort_sh = ab;
             if (ab) __hip_atomic_store(&a.st->fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         if (abort_sh) return;
         const int64_t forced = it < a.n_seeds ? a.seeds[it] : -1;
-        if (!select_lean<DIM>(a, forced, n, target2, n_iter, Eb[par], Pb[par], s, u, p, d, c)) break;
+        if (!select_lean<DIM, RES>(a, forced, n, target2, n_iter, Eb[par], Pb[par], s, u, p, d, c, xp)) break;
         pending = true;
     }
 }
@@ -1025,13 +1142,25 @@ __global__ void g_finite(const double *a, int64_t n, int32_t *bad)
 }
 
 // Holds G workgroups of the context's co-residency budget while a persistent kernel runs.
+// Persistent kernels of one context share the device through these tickets: g workgroups of a
+// kernel with room for cap on the device. try_alone takes the device for this kernel alone when no
+// other persistent kernel runs (alone is then set; nothing else starts until it ends), for a
+// kernel whose workgroups each need most of a compute unit's LDS; otherwise the ticket waits for
+// room as usual.
 struct CoopTicket {
+    static constexpr int64_t ALONE = int64_t(1) << 40;
     rbf_ctx ctx;
     int64_t units;
-    CoopTicket(rbf_ctx c, int64_t g, int64_t cap) : ctx(c), units(g)
+    bool alone = false;
+    CoopTicket(rbf_ctx c, int64_t g, int64_t cap, bool try_alone = false) : ctx(c), units(g)
     {
         std::unique_lock<std::mutex> lk(ctx->coop_mu);
-        ctx->coop_cv.wait(lk, [&] { return ctx->coop_in_use + units <= cap; });
+        if (try_alone && ctx->coop_in_use == 0) {
+            units = ALONE;
+            alone = true;
+        } else {
+            ctx->coop_cv.wait(lk, [&] { return ctx->coop_in_use + units <= cap; });
+        }
         ctx->coop_in_use += units;
     }
     ~CoopTicket()
@@ -1133,8 +1262,14 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
                    : (mode_env && !strcmp(mode_env, "lean")) ? 0
                    : (g > LEAN_MAX_TILES ? 2 : 0);
     const int coop_max = mode == 2 ? 0
-                       : cooperative_blocks(mode == 0 ? (const void *)g_level_lean<DIM> : (const void *)g_level<DIM>,
+                       : cooperative_blocks(mode == 0 ? (const void *)g_level_lean<DIM, false> : (const void *)g_level<DIM>,
                                             ctx->n_cu);
+    // The resident form of the persistent kernel (one tile per workgroup, its first RES_COLS
+    // Newton columns in LDS: about 115 KB per workgroup) when the device has room for a
+    // workgroup per tile; RBF_GREEDY_RESIDENT=0 keeps the plain form.
+    const char *res_env = getenv("RBF_GREEDY_RESIDENT");
+    const int coop_res = (mode == 0 && !(res_env && res_env[0] == '0'))
+                             ? cooperative_blocks((const void *)g_level_lean<DIM, true>, ctx->n_cu) : 0;
     DevBuf bBar, bE2, bPart2;
     RBF_TRY(bBar.get(pool, sizeof(GridBar), s));
     if (mode == 0 && coop_max > 0) {
@@ -1273,13 +1408,14 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
             const unsigned G = (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, gmax));
             // Persistent kernels of concurrent requests must fit on the device together, or their
             // spinning workgroups could wait for each other's unscheduled ones.
-            CoopTicket gate(ctx, G, coop_max);
+            CoopTicket gate(ctx, G, coop_max, mode == 0 && (int64_t)G == g && g <= coop_res);
             hipError_t e;
             if (mode == 0) {
                 RBF_HIP(hipMemsetAsync(bBar.ptr, 0, sizeof(GridBar), s));
                 GridBar *barp = bBar.as<GridBar>();
                 void *args[] = {&a, &barp};
-                e = hipLaunchCooperativeKernel((const void *)g_level_lean<DIM>, dim3(G), dim3(NT), args, 0, s);
+                const void *kern = gate.alone ? (const void *)g_level_lean<DIM, true> : (const void *)g_level_lean<DIM, false>;
+                e = hipLaunchCooperativeKernel(kern, dim3(G), dim3(NT), args, 0, s);
             } else {
                 void *args[] = {&a};
                 e = hipLaunchCooperativeKernel((const void *)g_level<DIM>, dim3(G), dim3(NT), args, 0, s);

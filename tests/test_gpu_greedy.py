@@ -304,3 +304,39 @@ def test_greedy_every_schedule_matches_oracle(gctx, orc, monkeypatch, mode, case
 
 
 _SCHEDULE_REF = {}
+
+
+@pytest.mark.parametrize("case", ["cfg1", "seeded100", "seeded250"])
+def test_greedy_resident_form_same_bits(gctx, monkeypatch, case):
+    """The resident persistent form (one tile per workgroup, its first 192 Newton columns in LDS,
+    the tile's error, coordinates and selected flags in registers) runs the plain persistent
+    form's arithmetic in the same order, so both give the same control sets, weights, final error
+    and error history bit for bit. cfg1 has levels of 17, 52 and 173 columns; the seeded cases
+    start a level from 100 seeds (columns filled into LDS at entry, then appended) and from 250
+    (more than LDS holds: the columns stream from the basis, the rest stays resident)."""
+    if case == "cfg1":
+        w = synth.workload_cfg1()
+        seeds = w.seeds
+    else:
+        n0 = int(case[len("seeded"):])
+        w = synth.random_workload(90 + n0, 2, 3000, 10, [0.3, 0.08], 1e-7, cap=900)
+        rng = np.random.default_rng(n0)
+        seeds = [[int(p) for p in rng.choice(w.n_s, size=n0, replace=False)], []]
+    outs = {}
+    for res in ("1", "0"):
+        monkeypatch.setenv("RBF_GREEDY_MODE", "lean")
+        monkeypatch.setenv("RBF_GREEDY_RESIDENT", res)
+        print(f"case {case} n_s={w.n_s} resident={res}", flush=True)
+        cs = rbfdef.rbf_greedy_select(gctx, to_dev(w.xs), to_dev(w.ds), w.radius, w.eps, rho=w.rho,
+                                      cap=w.cap_total(), seeds=seeds)
+        torch.cuda.synchronize()
+        outs[res] = cs
+    a, b = outs["1"], outs["0"]
+    print(f"levels {a.level_off} stops {a.level_stop[: a.n_levels_used]}", flush=True)
+    assert a.level_off == b.level_off and a.level_stop == b.level_stop
+    assert a.total > len(seeds[0])
+    for x, y in ((a.ctrl_idx[: a.total], b.ctrl_idx[: b.total]), (a.alpha[:, : a.total], b.alpha[:, : b.total]),
+                 (a.e_final, b.e_final), (a.err_hist, b.err_hist)):
+        x, y = x.cpu().numpy(), y.cpu().numpy()
+        assert np.array_equal(x.view(np.uint64) if x.dtype == np.float64 else x,
+                              y.view(np.uint64) if y.dtype == np.float64 else y)
