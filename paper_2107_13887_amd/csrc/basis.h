@@ -29,7 +29,8 @@ __device__ __forceinline__ T wendland_t(T eta, T t)
 }
 
 // The same functions written in t alone (eta = 1 - t), for a caller that forms t without eta:
-// tc = max(t, 0) carries the compact support and t (unclamped) the polynomial factor:
+// tc = max(t, 0) carries the compact support and t the polynomial factor (t may be tc itself:
+// where they differ the product is zero either way):
 //   C0: tc^2,  C2: tc^4 (5 - 4 t),  C4: tc^6 (35/3 t^2 - 88/3 t + 56/3),
 //   C6: tc^8 (-32 t^3 + 121 t^2 - 154 t + 66).
 template <int BASIS, typename T>

@@ -3,7 +3,7 @@
 //
 //   out_k(p) = base_k(p) - sign * sum_l psi(d_p / D_l) sum_{c in level l} phi(||x_p - x_c|| / R_l) alpha_k,c
 //
-// Design (VALU-bound: about 22 vector slots per point/control pair in 2D, 25 in 3D, three fewer
+// Design (VALU-bound: about 21 vector slots per point/control pair in 2D, 24 in 3D, three fewer
 // in the volume sums, against 40-56 bytes of HBM traffic per point):
 //   * points stream as SoA, P points per lane, 256 lanes per workgroup, each wave on 64 P
 //     consecutive stored points;
@@ -79,6 +79,9 @@ __device__ __forceinline__ void split_range(const SumLevel &L, int s, int S, int
 
 // One pair in FP64: phi(|q - c|) for coordinates already scaled by 1/R (Table 1), the root to
 // half an ulp.
+// Every pair form below clamps t = 1 - eta with fmin(fmax(t, 0), 1), which the compiler folds into
+// the clamp modifier of the instruction that forms t (t <= 1 always: eta >= 0), so the compact
+// support costs no instruction of its own.
 template <int DIM, int BASIS>
 __device__ __forceinline__ double pair_f64(const double (&q)[DIM], const double *c)
 {
@@ -90,7 +93,7 @@ __device__ __forceinline__ double pair_f64(const double (&q)[DIM], const double 
         r2 = __builtin_fma(dk, dk, r2);
     }
     double eta = sqrt_goldschmidt(r2);
-    double t = fmax(1.0 - eta, 0.0);
+    double t = fmin(fmax(1.0 - eta, 0.0), 1.0);
     return wendland_t<BASIS, double>(eta, t);
 }
 
@@ -111,8 +114,8 @@ __device__ __forceinline__ double pair_f64_t(const double (&q)[DIM], const doubl
     const double y = __builtin_amdgcn_rsq(s);
     const double G = s * y;
     const double r = __builtin_fma(-G, y, 1.0);
-    const double t = __builtin_fma(G, __builtin_fma(r, -0.25, -0.5), 1.0);
-    return wendland_tform<BASIS, double>(fmax(t, 0.0), t);
+    const double tc = fmin(fmax(__builtin_fma(G, __builtin_fma(r, -0.25, -0.5), 1.0), 0.0), 1.0);
+    return wendland_tform<BASIS, double>(tc, tc);
 }
 
 template <int DIM, int BASIS>
@@ -126,7 +129,7 @@ __device__ __forceinline__ float pair_f32(const float (&q)[DIM], const float *c)
         r2 = __builtin_fmaf(dk, dk, r2);
     }
     float eta = __builtin_amdgcn_sqrtf(r2);
-    float t = fmaxf(1.0f - eta, 0.0f);
+    float t = fminf(fmaxf(1.0f - eta, 0.0f), 1.0f);
     return wendland_t<BASIS, float>(eta, t);
 }
 
