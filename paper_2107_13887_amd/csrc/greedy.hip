@@ -55,6 +55,10 @@ constexpr int NT = UPB * UWAVES;
 constexpr int LCHUNK = 2048;  // Newton row entries staged per LDS pass
 constexpr int64_t LEAN_MAX_TILES = 256;   // largest surface (in tiles) run by the persistent kernel
 constexpr int RES_COLS = 192;             // Newton columns a resident persistent workgroup keeps in LDS
+// The two-launch update reads the basis columns below keep_cols with the default cache policy and
+// the rest non-temporally, so that the first KEEP_BYTES of every iteration's stream stay in the
+// 256 MB last-level cache for the next iteration instead of being evicted by the rest of it.
+constexpr int64_t KEEP_BYTES = int64_t(192) << 20;
 constexpr int64_t SEED_FACTOR_MIN = 32;   // fewest seeds of a level started from the blocked factor
 
 struct GState {
@@ -100,6 +104,7 @@ struct GArgs {
     const int64_t *seeds;  // device [n_seeds]
     int64_t n_seeds;
     int64_t max_iter;
+    int64_t keep_cols;   // two-launch update: columns read with the default cache policy (KEEP_BYTES)
 };
 
 struct SelShared {
@@ -407,10 +412,25 @@ __device__ void update_tile(const GArgs &a, int64_t tile, int64_t n, int64_t p, 
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         // Sixteen column loads in flight per lane before any is consumed: the loop is bound by
         // memory, not by the multiply-adds.
-        for (; j + 16 <= je; j += 16, col += 16 * UPB) {
+        // Blocks of 16 wholly below keep_cols take the default cache policy, the rest are read
+        // non-temporally; the sums run in the same order either way.
+        const int64_t jk = a.keep_cols - j0;
+        for (; j + 16 <= je && j + 16 <= jk; j += 16, col += 16 * UPB) {
             double v[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) v[q] = col[q * UPB];
+#pragma unroll
+            for (int q = 0; q < 16; q += 4) {
+                s0 = __builtin_fma(v[q], u.lsh[j + q], s0);
+                s1 = __builtin_fma(v[q + 1], u.lsh[j + q + 1], s1);
+                s2 = __builtin_fma(v[q + 2], u.lsh[j + q + 2], s2);
+                s3 = __builtin_fma(v[q + 3], u.lsh[j + q + 3], s3);
+            }
+        }
+        for (; j + 16 <= je; j += 16, col += 16 * UPB) {
+            double v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = __builtin_nontemporal_load(col + q * UPB);
 #pragma unroll
             for (int q = 0; q < 16; q += 4) {
                 s0 = __builtin_fma(v[q], u.lsh[j + q], s0);
@@ -1293,6 +1313,8 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     a.part2 = bPart2.as<Cand>();
     a.spin_limit = LEAN_SPIN_LIMIT;
     if (const char *e = getenv("RBF_GREEDY_SPIN_LIMIT")) a.spin_limit = strtoull(e, nullptr, 10);
+    a.keep_cols = (KEEP_BYTES / (int64_t)(sizeof(double) * n_s)) / 16 * 16;
+    if (const char *e = getenv("RBF_GREEDY_KEEP_COLS")) a.keep_cols = strtoll(e, nullptr, 10);
     a.g = g;
     a.hist = bHist.as<double>();
     a.hist_cap = cap;
