@@ -21,9 +21,9 @@
 // in which every workgroup runs the select phase itself after the iteration's one grid barrier,
 // keeping the Newton row in LDS for its update. When the device holds a workgroup per tile and no
 // other persistent kernel runs, the resident form also keeps each tile's first Newton columns in
-// LDS and its error in registers, and passes what workgroups read from each other through
-// coherent accesses, so that its barrier needs no cache maintenance. On large surfaces (or when a
-// cooperative launch is impossible) the two phases run as two kernel launches per iteration.
+// LDS and its error in registers, so that its update reads no global memory. On large surfaces
+// (or when a cooperative launch is impossible) the two phases run as two kernel launches per
+// iteration.
 // Reductions run in a fixed order; squared norms are formed without fused multiply-adds so they
 // equal the textbook formula term by term.
 //
@@ -55,6 +55,7 @@ constexpr int NT = UPB * UWAVES;
 constexpr int LCHUNK = 2048;  // Newton row entries staged per LDS pass
 constexpr int64_t LEAN_MAX_TILES = 256;   // largest surface (in tiles) run by the persistent kernel
 constexpr int RES_COLS = 192;             // Newton columns a resident persistent workgroup keeps in LDS
+constexpr int SEL_U = 8;                  // loads a select thread issues before using any
 // The two-launch update reads the basis columns below keep_cols with the default cache policy and
 // the rest non-temporally, so that the first KEEP_BYTES of every iteration's stream stay in the
 // 256 MB last-level cache for the next iteration instead of being evicted by the rest of it.
@@ -156,23 +157,6 @@ __device__ __forceinline__ double phi_pair(const double *xs, int64_t ld, int64_t
     double eta = sqrt(s) / R;
     if (eta >= 1.0) return 0.0;
     return wendland(basis, eta);
-}
-
-// Agent-scope relaxed accesses (global_load / global_store with sc1): coherent across the XCDs'
-// L2 caches for the location itself, with no cache write-back or invalidation. The resident
-// persistent form passes everything one workgroup reads from another (the tile maxima, the error
-// at the selected row, the Newton columns) through these, so its barrier needs no release or
-// acquire fence.
-template <typename T>
-__device__ __forceinline__ T ld_coh(const T *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename T>
-__device__ __forceinline__ void st_coh(T *p, T v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // phi_pair on coordinates already at hand, with the same arithmetic.
@@ -295,12 +279,20 @@ __device__ void select_phase(const GArgs &a, int64_t forced, SelShared &s)
     if (forced < 0) {
         double bm = -1.0;
         int64_t bi = -1;
-        for (int64_t b = threadIdx.x; b < a.g; b += NT) {
-            const Cand c = a.part[b];
-            if (better(c.m2, c.idx, bm, bi)) {
-                bm = c.m2;
-                bi = c.idx;
+        // SEL_U maxima per thread in flight at once, then compared in the same order.
+        for (int64_t b0 = threadIdx.x; b0 < a.g; b0 += (int64_t)NT * SEL_U) {
+            Cand cv[SEL_U];
+#pragma unroll
+            for (int r = 0; r < SEL_U; ++r) {
+                const int64_t b = b0 + (int64_t)r * NT;
+                cv[r] = b < a.g ? a.part[b] : Cand{-1.0, -1};
             }
+#pragma unroll
+            for (int r = 0; r < SEL_U; ++r)
+                if (better(cv[r].m2, cv[r].idx, bm, bi)) {
+                    bm = cv[r].m2;
+                    bi = cv[r].idx;
+                }
         }
         wave_argmax(bm, bi);
         if (lane == 0) s.sh[w] = Cand{bm, bi};
@@ -347,11 +339,25 @@ __device__ void select_phase(const GArgs &a, int64_t forced, SelShared &s)
     if (threadIdx.x == 0)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) ep[k] = a.E[k * a.n_s + p];
+    // The row's entries (one per 512-byte column of p's tile): SEL_U loads per thread in flight
+    // before any is stored or summed, the sum in increasing j as before.
+    const double *prow = a.V + (p / UPB) * a.ldt * UPB + (p % UPB);
     double part_ll = 0.0;
-    for (int64_t j = threadIdx.x; j < n; j += NT) {
-        const double v = a.V[((p / UPB) * a.ldt + j) * UPB + (p % UPB)];
-        row[j] = v;
-        part_ll = __builtin_fma(v, v, part_ll);
+    for (int64_t j0 = threadIdx.x; j0 < n; j0 += (int64_t)NT * SEL_U) {
+        double v[SEL_U];
+#pragma unroll
+        for (int r = 0; r < SEL_U; ++r) {
+            const int64_t j = j0 + (int64_t)r * NT;
+            v[r] = j < n ? prow[j * UPB] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < SEL_U; ++r) {
+            const int64_t j = j0 + (int64_t)r * NT;
+            if (j < n) {
+                row[j] = v[r];
+                part_ll = __builtin_fma(v[r], v[r], part_ll);
+            }
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) part_ll += __shfl_xor(part_ll, off, 64);
@@ -578,7 +584,8 @@ __device__ __forceinline__ double slice_dot(const double *col, const double *l, 
 
 // What a resident workgroup keeps of its tile's row in each lane between iterations: the error as
 // it last wrote it, the coordinates, and whether the row was selected in this level (or lies past
-// the surface). With its first RES_COLS Newton columns in LDS, an update reads no global memory.
+// the surface). With its first RES_COLS Newton columns in LDS, an update of up to RES_COLS columns
+// reads no global memory.
 template <int DIM>
 struct ResRow {
     double e[DIM];
@@ -605,7 +612,7 @@ __device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_
         if (!row_in_lds) {
             __syncthreads();
             for (int t = threadIdx.x; t < nj; t += NT)
-                u.lsh[t] = RES ? ld_coh(&prow[(j0 + t) * UPB]) : prow[(j0 + t) * UPB];
+                u.lsh[t] = prow[(j0 + t) * UPB];
             __syncthreads();
         }
         const int per = (nj + UWAVES - 1) / UWAVES;
@@ -626,19 +633,14 @@ __device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_
             for (int k = 1; k < UWAVES; ++k) dot += u.psum[k][lane];
             const double ph = RES ? phi_xy<DIM>(rr.x, xp, a.R, a.basis) : phi_pair<DIM>(a.xs, a.n_s, i, p, a.R, a.basis);
             const double v = (ph - dot) / d;
-            if (RES) st_coh(&a.V[(tile * a.ldt + n) * UPB + lane], v);
-            else a.V[(tile * a.ldt + n) * UPB + lane] = v;
+            a.V[(tile * a.ldt + n) * UPB + lane] = v;
             if (RES && n < RES_COLS) vres[n * UPB + lane] = v;
             double e[DIM];
 #pragma unroll
             for (int k = 0; k < DIM; ++k) {
                 e[k] = __builtin_fma(-c[k], v, RES ? rr.e[k] : Ein[k * a.n_s + i]);
-                if (RES) {
-                    st_coh(&Eout[k * a.n_s + i], e[k]);
-                    rr.e[k] = e[k];
-                } else {
-                    Eout[k * a.n_s + i] = e[k];
-                }
+                Eout[k * a.n_s + i] = e[k];
+                if (RES) rr.e[k] = e[k];
             }
             if (RES ? !rr.sel : (i != p && !a.sel[i])) {
 #pragma clang fp contract(off)
@@ -650,14 +652,7 @@ __device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_
             }
         }
         wave_argmax(m2, idx);
-        if (lane == 0) {
-            if (RES) {
-                st_coh(&part_out[tile].m2, m2);
-                st_coh(&part_out[tile].idx, idx);
-            } else {
-                part_out[tile] = Cand{m2, idx};
-            }
-        }
+        if (lane == 0) part_out[tile] = Cand{m2, idx};
     }
 }
 
@@ -676,12 +671,19 @@ __device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double ta
     if (forced < 0) {
         double bm = -1.0;
         int64_t bi = -1;
-        for (int64_t b = threadIdx.x; b < a.g; b += NT) {
-            const Cand c = RES ? Cand{ld_coh(&part[b].m2), ld_coh(&part[b].idx)} : part[b];
-            if (better(c.m2, c.idx, bm, bi)) {
-                bm = c.m2;
-                bi = c.idx;
+        for (int64_t b0 = threadIdx.x; b0 < a.g; b0 += (int64_t)NT * SEL_U) {
+            Cand cv[SEL_U];
+#pragma unroll
+            for (int r = 0; r < SEL_U; ++r) {
+                const int64_t b = b0 + (int64_t)r * NT;
+                cv[r] = b < a.g ? part[b] : Cand{-1.0, -1};
             }
+#pragma unroll
+            for (int r = 0; r < SEL_U; ++r)
+                if (better(cv[r].m2, cv[r].idx, bm, bi)) {
+                    bm = cv[r].m2;
+                    bi = cv[r].idx;
+                }
         }
         wave_argmax(bm, bi);
         if (lane == 0) s.sh[w] = Cand{bm, bi};
@@ -725,16 +727,27 @@ __device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double ta
     if (threadIdx.x == 0)
 #pragma unroll
         for (int k = 0; k < DIM; ++k) {
-            ep[k] = RES ? ld_coh(&Ecur[k * a.n_s + p]) : Ecur[k * a.n_s + p];
+            ep[k] = Ecur[k * a.n_s + p];
             xp[k] = a.xs[k * a.n_s + p];
         }
     const double *prow = a.V + (p / UPB) * a.ldt * UPB + (p % UPB);
     double part_ll = 0.0;
-    for (int64_t j = threadIdx.x; j < n; j += NT) {
-        const double v = RES ? ld_coh(&prow[j * UPB]) : prow[j * UPB];
-        if (j < LCHUNK) u.lsh[j] = v;
-        if (writer) row[j] = v;
-        part_ll = __builtin_fma(v, v, part_ll);
+    for (int64_t j0 = threadIdx.x; j0 < n; j0 += (int64_t)NT * SEL_U) {
+        double v[SEL_U];
+#pragma unroll
+        for (int r = 0; r < SEL_U; ++r) {
+            const int64_t j = j0 + (int64_t)r * NT;
+            v[r] = j < n ? prow[j * UPB] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < SEL_U; ++r) {
+            const int64_t j = j0 + (int64_t)r * NT;
+            if (j < n) {
+                if (j < LCHUNK) u.lsh[j] = v[r];
+                if (writer) row[j] = v[r];
+                part_ll = __builtin_fma(v[r], v[r], part_ll);
+            }
+        }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) part_ll += __shfl_xor(part_ll, off, 64);
@@ -846,18 +859,9 @@ __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
             pending = false;
         }
         // Grid barrier: one release per arrival, relaxed polls of the arrival count, one acquire.
-        // The resident form's cross-workgroup data all moves by coherent accesses (ld_coh /
-        // st_coh, issued by wave 0 in the update), so its arrival only waits for those stores to
-        // complete and its departure needs no invalidation.
         __syncthreads();
         if (threadIdx.x == 0) {
-            if constexpr (RES) {
-                __atomic_signal_fence(__ATOMIC_SEQ_CST);
-                __builtin_amdgcn_s_waitcnt(0);
-                __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            } else {
-                __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned int target = nb * (unsigned int)(it + 1);
             unsigned long long spins = 0;
             int32_t ab = 0;
@@ -868,8 +872,7 @@ __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
                 }
                 __builtin_amdgcn_s_sleep(1);
             }
-            if constexpr (RES) __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             abort_sh = ab;
             if (ab) __hip_atomic_store(&a.st->fault, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
