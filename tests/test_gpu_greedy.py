@@ -340,3 +340,26 @@ def test_greedy_resident_form_same_bits(gctx, monkeypatch, case):
         x, y = x.cpu().numpy(), y.cpu().numpy()
         assert np.array_equal(x.view(np.uint64) if x.dtype == np.float64 else x,
                               y.view(np.uint64) if y.dtype == np.float64 else y)
+
+
+def test_greedy_cache_policy_split_same_bits(gctx, monkeypatch):
+    """The two-launch update reads the basis columns below keep_cols with the default cache policy
+    and the rest non-temporally, split on whole blocks of 16 columns: every split (none kept, the
+    default, a split inside a wave's slice, all kept) gives the same bits."""
+    w = synth.workload_cfg1()
+    monkeypatch.setenv("RBF_GREEDY_MODE", "kernels")
+    outs = []
+    for keep in ("0", None, "37", "1000000"):
+        if keep is None:
+            monkeypatch.delenv("RBF_GREEDY_KEEP_COLS", raising=False)
+        else:
+            monkeypatch.setenv("RBF_GREEDY_KEEP_COLS", keep)
+        print(f"case cfg1 two launches keep_cols={keep or 'default'}", flush=True)
+        cs = rbfdef.rbf_greedy_select(gctx, to_dev(w.xs), to_dev(w.ds), w.radius, w.eps, rho=w.rho,
+                                      cap=w.cap_total(), seeds=w.seeds)
+        torch.cuda.synchronize()
+        outs.append((cs.ctrl_idx[: cs.total].cpu().numpy(), cs.alpha[:, : cs.total].cpu().numpy().view(np.uint64),
+                     cs.e_final.cpu().numpy().view(np.uint64)))
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y)
