@@ -660,7 +660,7 @@ __device__ void update_tile_lean(const GArgs &a, int64_t tile, int64_t n, int64_
 // barrier: the next point (argmax of the per-tile maxima, or a forced seed), the stop tests, the
 // Newton row l = V[p, 0:n] (kept in LDS for the update when it fits), the pivot and the Newton
 // coefficients. Workgroup 0 writes the outputs. Returns false when the level stops.
-template <int DIM, bool RES>
+template <int DIM>
 __device__ bool select_lean(const GArgs &a, int64_t forced, int64_t n, double target2, int64_t &n_iter,
                             const double *Ecur, const Cand *part, SelShared &s, UpdShared &u,
                             int64_t &p_out, double &d_out, double (&c_out)[DIM], double (&xp_out)[DIM])
@@ -879,7 +879,7 @@ __global__ __launch_bounds__(NT) void g_level_lean(GArgs a, GridBar *bar)
         __syncthreads();
         if (abort_sh) return;
         const int64_t forced = it < a.n_seeds ? a.seeds[it] : -1;
-        if (!select_lean<DIM, RES>(a, forced, n, target2, n_iter, Eb[par], Pb[par], s, u, p, d, c, xp)) break;
+        if (!select_lean<DIM>(a, forced, n, target2, n_iter, Eb[par], Pb[par], s, u, p, d, c, xp)) break;
         pending = true;
     }
 }
