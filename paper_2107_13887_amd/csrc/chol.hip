@@ -479,6 +479,9 @@ __global__ __launch_bounds__(256, 2) void c_seed_basis(const double *xs, int64_t
         for (int k = 0; k < DIM; ++k) xt[k][t] = xs[k * n_s + i];
     }
     for (int64_t kb = 0; kb < nblk; ++kb) {
+        // The previous block of V was stored to global memory by every thread at the end of the
+        // previous iteration; the loads below read it (block 0 at kb = 1) in other threads.
+        __syncthreads();
         d4 acc[2][2];
 #pragma unroll
         for (int r = 0; r < 2; ++r)

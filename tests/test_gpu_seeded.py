@@ -121,3 +121,23 @@ def test_warm_start_without_room_for_bases(gctx, orc, monkeypatch):
         prev = [list(ref.level(l)[0]) for l in range(ref.n_levels_used)]
         prev += [[] for _ in range(w.n_levels - len(prev))]
     rbfdef.rbf_geom_release(gctx, geom)
+
+
+@pytest.mark.parametrize("n0", [100, 250])
+def test_seeded_start_repeats_bit_for_bit(gctx, monkeypatch, n0):
+    """The blocked seeded start reads back, in other threads, the blocks of V each workgroup has
+    just stored; a barrier orders them. Two calls on the same seeds, with calls on other inputs
+    between them (so the pool hands back memory holding other values), must give the same bits."""
+    w = synth.random_workload(90 + n0, 2, 3000, 10, [0.3, 0.08], 1e-7, cap=900)
+    rng = np.random.default_rng(n0)
+    seeds = [[int(p) for p in rng.choice(w.n_s, size=n0, replace=False)], []]
+    other = synth.random_workload(7 + n0, 2, 3000, 10, [0.3, 0.08], 1e-7, cap=900)
+    outs = []
+    for rep in range(2):
+        print(f"case n0={n0} call {rep}", flush=True)
+        cs = _seeded(gctx, w, seeds, "factor", monkeypatch)
+        outs.append((_ctrl(cs), cs.alpha[:, : cs.total].cpu().numpy().view(np.uint64),
+                     cs.e_final.cpu().numpy().view(np.uint64)))
+        _seeded(gctx, other, [list(range(0, 2 * n0, 2)), []], "factor", monkeypatch)
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y)
