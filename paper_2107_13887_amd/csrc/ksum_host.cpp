@@ -2,6 +2,7 @@
 // lane, control-list splits), the resident geometry's row-group order, timers and the
 // evaluated-pair counter.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 
 #include "ksum.h"
@@ -44,11 +45,12 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s, cons
     a.n_live = -1;
     a.n_levels = pb.n_levels;
     int64_t nc_max = 0;
-    double dmax = 0.0;
+    double dmax = 0.0, dmin = HUGE_VAL;
     for (int l = 0; l < pb.n_levels; ++l) {
         a.lv[l] = pb.lv[l];
         nc_max = std::max<int64_t>(nc_max, pb.lv[l].c_end - pb.lv[l].c_begin);
         dmax = std::max(dmax, pb.lv[l].D);
+        if (pb.lv[l].c_end > pb.lv[l].c_begin) dmin = std::min(dmin, pb.lv[l].D);
     }
     a.xc = pb.xc;
     a.alpha = pb.alpha;
@@ -118,9 +120,12 @@ rbf_status run_kernel_sum(rbf_ctx ctx, const SumProblem &pb, hipStream_t s, cons
     for (int l = 0; l < pb.n_levels; ++l) mixed |= pb.lv[l].fp32 != 0;
     // Two points per lane share every control read from LDS; one point per lane gives twice the
     // workgroups, which balances better when there are few blocks (the cost of a block varies
-    // with the number of controls near it).
+    // with the number of controls near it), and waves of half the rows, of which fewer straddle a
+    // level's support distance when the levels' distances differ (a wave that needs a level
+    // computes all its rows for it, psi = 0 on those beyond).
     const ShapeEnv &env = shape_env();
-    int P = env.P ? env.P : (n_rows < (int64_t)8 * ctx->n_cu * VBLOCK ? 1 : 2);
+    const bool uneven_d = pb.dwall && dmax > 2.0 * dmin;
+    int P = env.P ? env.P : (n_rows < (int64_t)8 * ctx->n_cu * VBLOCK || uneven_d ? 1 : 2);
     if (P != 1 && P != 2) P = 2;
     const int64_t nbx = (n_rows + (int64_t)BLOCK * P - 1) / ((int64_t)BLOCK * P);
     const int64_t target = env.blocks > 0 ? env.blocks : (int64_t)8 * ctx->n_cu;
