@@ -53,7 +53,7 @@ constexpr int UPB = 64;       // surface points per tile (one per lane)
 constexpr int UWAVES = 4;     // waves per workgroup, each a slice of the dot product
 constexpr int NT = UPB * UWAVES;
 constexpr int LCHUNK = 2048;  // Newton row entries staged per LDS pass
-constexpr int64_t LEAN_MAX_TILES = 256;   // largest surface (in tiles) run by the persistent kernel
+constexpr int64_t LEAN_MAX_TILES = 112;   // largest surface (in tiles) run by the persistent kernel
 constexpr int RES_COLS = 192;             // Newton columns a resident persistent workgroup keeps in LDS
 constexpr int SEL_U = 8;                  // loads a select thread issues before using any
 // The two-launch update reads the basis columns below keep_cols with the default cache policy and
@@ -1268,11 +1268,13 @@ rbf_status greedy_impl(rbf_ctx ctx, const rbf_greedy_params &prm, int64_t n_s, c
     RBF_HIP(hipMemcpyAsync(R, ds, sizeof(double) * DIM * n_s, hipMemcpyDeviceToDevice, s));
 
     // Execution mode: "lean" (one barrier per iteration), "cg" (cooperative-groups grid
-    // barriers) or "kernels" (two launches per iteration). Default: the persistent kernel while the surface has at most LEAN_MAX_TILES tiles (one
-    // workgroup per CU; latency-bound iterations, where launches would dominate), two launches per
-    // iteration beyond that: there the basis stream is the cost, and fresh launches stream it at
-    // about twice the rate of the persistent kernel, whose per-workgroup release and acquire each
-    // iteration write back and invalidate the L2 of every XCD.
+    // barriers) or "kernels" (two launches per iteration). Default: the persistent kernel while the
+    // surface has at most LEAN_MAX_TILES tiles (latency-bound iterations, where launches would
+    // dominate), two launches per iteration beyond that: there the basis stream is the cost, and
+    // fresh launches stream it faster than the persistent kernel, whose per-workgroup release and
+    // acquire each iteration write back and invalidate the L2 of every XCD. The two cost the same
+    // near 110 tiles on a three-level wing (measured: 94 tiles 53 vs 55 ms, 120 tiles 56.9 vs
+    // 56.2 ms, 188 tiles 94.6 vs 86.6 ms, persistent vs two launches).
     // Seeded starts: blocked factor from SEED_FACTOR_MIN seeds on; RBF_SEED_START=append|factor
     // forces one form (tests and timing).
     int64_t seed_factor_min = SEED_FACTOR_MIN;
