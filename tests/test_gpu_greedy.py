@@ -363,3 +363,15 @@ def test_greedy_cache_policy_split_same_bits(gctx, monkeypatch):
     for o in outs[1:]:
         for x, y in zip(outs[0], o):
             assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("tiles", [112, 113])
+def test_greedy_default_schedule_either_side_of_the_switch(gctx, orc, monkeypatch, tiles):
+    """With no schedule named, a surface of at most 112 tiles of 64 points runs the persistent
+    kernel and a larger one two launches per iteration: the oracle's control points on both sides
+    of the switch (3D, a ragged last tile on the larger side)."""
+    monkeypatch.delenv("RBF_GREEDY_MODE", raising=False)
+    monkeypatch.delenv("RBF_NO_COOP", raising=False)
+    w = synth.random_workload(21, 3, 64 * tiles - (0 if tiles == 112 else 37), 10, [0.3], 0.0, cap=160)
+    ref, cs = _greedy_both(gctx, orc, w)
+    _check_same(orc, w, ref, cs)
